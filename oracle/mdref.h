@@ -1,0 +1,126 @@
+/*
+ * mdref.h -- plain, slow, FP64 CPU oracle for the short-range MD hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no source,
+ * header, table or helper with the HIP library (paper_1105_5613_amd/csrc).
+ *
+ * What it computes (Allsopp, Ruocco, Fratalocchi, "Molecular dynamics
+ * beyonds the limits", arXiv:1105.5613):
+ *   - pair potentials: Lennard-Jones Eq. (1), soft sphere Eq. (2), with the
+ *     truncated shifted-force form Eq. (3) (section "Interaction potential");
+ *   - forces as the plain O(N^2) sum over all pairs under the minimum-image
+ *     convention, each pair once with Newton's third law (section
+ *     "Grid-search method");
+ *   - an independent cell list of cubic cells of side >= cutoff (Fig. 1 and
+ *     "Interaction potential"), and a full neighbour list with a skin;
+ *   - velocity-Verlet time marching (section "Parallel force calculation");
+ *   - an isokinetic velocity rescale for the canonical (fixed-T) runs
+ *     ("BBMD scaling results") and a linear temperature ramp (glass section).
+ *
+ * Conventions: positions/velocities/forces are [n][3] row-major doubles;
+ * species are int32 in [0, ntypes); per-pair tables are [a*4 + b].
+ * Every function returns 0 on success and a negative value on invalid input.
+ */
+#ifndef MDREF_H
+#define MDREF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MDREF_MAXT 4
+
+typedef struct {
+  int32_t ntypes;     /* 1..4 */
+  int32_t potential;  /* 0 = Lennard-Jones Eq. (1), 1 = soft sphere Eq. (2) */
+  int32_t trunc;      /* 0 = shifted force Eq. (3), 1 = energy shift only */
+  int32_t pad;
+  double eps[16];     /* eps[a*4+b], symmetric */
+  double sig[16];     /* sigma[a*4+b], symmetric */
+  double rc[16];      /* cutoff per species pair */
+  double mass[4];
+  double skin;        /* neighbour-list skin; 0 = rebuild every step */
+} mdref_params;
+
+typedef struct {
+  double ke, pe, w, T, P, E, max_disp2;
+  int64_t step;
+  int32_t rebuilt;
+  int32_t pad;
+} mdref_obs;
+
+/* Eq. (1)/(2): the untruncated potential and its radial derivative dV/dr. */
+double mdref_v(const mdref_params* p, int32_t a, int32_t b, double r);
+double mdref_dv(const mdref_params* p, int32_t a, int32_t b, double r);
+/* Eq. (3): truncated potential V*(r) and f(r) = -d(V*)/dr, zero for r >= rc. */
+int mdref_pair(const mdref_params* p, int32_t a, int32_t b, double r,
+               double* vstar, double* f);
+
+/* Brute force: all i<j, minimum image, Newton's third law.
+ * F [n][3] out; pe = sum V*, w = sum f(r) r.  Requires L >= 2 max rc. */
+int mdref_forces_brute(const mdref_params* p, int64_t n, double L,
+                       const double* x, const int32_t* type,
+                       double* F, double* pe, double* w);
+
+/* Cell grid: nc = floor(L / (max rc + skin)), nc < 3 -> 1; inv_cell = nc/L. */
+int mdref_cell_grid(const mdref_params* p, double L, int32_t* nc, double* inv_cell);
+
+/* Wrap x in place (one periodic wrap per coordinate, image counters kept in
+ * img [n][3] when not NULL), bin into cells and order particles by
+ * (cell id, particle id).  cell [n], cell_start [nc^3+1], order [n]. */
+int mdref_build_cells(int64_t n, double L, int32_t nc, double inv_cell,
+                      double* x, int32_t* img, int32_t* cell,
+                      int32_t* cell_start, int32_t* order);
+
+/* Full neighbour list over the 27-cell stencil: j in list(i) iff
+ * r^2 < (rc_ab + skin)^2.  Rows ids [n][cap] in traversal order, count [n]
+ * is the true count.  Returns 1 if any count exceeded cap. */
+int mdref_build_nlist(const mdref_params* p, int64_t n, double L, int32_t nc,
+                      const double* x, const int32_t* type,
+                      const int32_t* cell, const int32_t* cell_start,
+                      const int32_t* order, int32_t cap,
+                      int32_t* count, int32_t* ids);
+
+/* Forces from the list (full list, each pair seen from both sides). */
+int mdref_forces_list(const mdref_params* p, int64_t n, double L,
+                      const double* x, const int32_t* type, int32_t cap,
+                      const int32_t* count, const int32_t* ids,
+                      double* F, double* pe, double* w);
+
+/* Forces on a subset straight from the cell list (no neighbour list):
+ * sel [nsel] particle ids (NULL = all n).  F [nsel][3]; pe_i, w_i [nsel]
+ * per-particle halves (may be NULL).  x must be the wrapped positions that
+ * built the cells. */
+int mdref_forces_cells(const mdref_params* p, int64_t n, double L, int32_t nc,
+                       const double* x, const int32_t* type,
+                       const int32_t* cell, const int32_t* cell_start,
+                       const int32_t* order, int64_t nsel, const int64_t* sel,
+                       double* F, double* pe_i, double* w_i);
+
+/* Radial distribution function (glass section): histogram of pair
+ * distances r < rmax into nbins bins, normalised as g(r) = 2V/N^2 *
+ * <sum_{i<j} delta(r - r_ij)>.  Minimum image; requires rmax <= L/2. */
+int mdref_rdf(int64_t n, double L, const double* x, double rmax,
+              int32_t nbins, double* g);
+
+/* A full simulation: velocity Verlet with the skin rebuild rule. */
+typedef struct mdref_sim mdref_sim;
+mdref_sim* mdref_sim_create(const mdref_params* p, int64_t n, double L,
+                            double dt, int32_t brute);
+void mdref_sim_destroy(mdref_sim* s);
+int mdref_sim_set_state(mdref_sim* s, const double* x, const double* v,
+                        const int32_t* type);
+int mdref_sim_get_state(const mdref_sim* s, double* x, double* v, int32_t* img);
+int mdref_sim_get_forces(mdref_sim* s, double* F, double* pe, double* w);
+/* thermostat = 0: NVE.  Otherwise T_target(k) = T0 + (T1-T0) min(k/ramp, 1)
+ * for the k-th step of this call (ramp <= 0: T0). obs [nsteps] may be NULL. */
+int mdref_sim_step(mdref_sim* s, int32_t nsteps, int32_t thermostat,
+                   double T0, double T1, int64_t ramp, mdref_obs* obs);
+int64_t mdref_sim_rebuilds(const mdref_sim* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
