@@ -1,0 +1,194 @@
+/*
+ * md.h -- C ABI of the MI355X (gfx950) short-range molecular-dynamics hot path.
+ *
+ * The library advances periodic boxes of a binary (up to 4 species)
+ * Lennard-Jones or soft-sphere mixture with velocity Verlet, following
+ * Allsopp, Ruocco, Fratalocchi, arXiv:1105.5613:
+ *   - pair potential Eq. (1) (Lennard-Jones) or Eq. (2) (soft sphere), each
+ *     truncated in the shifted-force form Eq. (3) ("Interaction potential");
+ *   - cubic cells of side >= cutoff holding many particles each, searched
+ *     over neighbouring cells only (Fig. 1, "Grid-search method"); here the
+ *     cells feed a full neighbour list with a skin that is rebuilt when some
+ *     particle has moved more than half the skin;
+ *   - velocity-Verlet time marching ("Parallel force calculation");
+ *   - fixed-temperature (canonical) runs by isokinetic velocity rescaling and
+ *     linear temperature ramps (scaling-results and glass sections).
+ *
+ * One context holds `nrep` independent replicas (a single system is
+ * nrep = 1).  Replica r owns particles [off_r, off_r + n[r]) of every
+ * caller array, where off_r = n[0] + ... + n[r-1].
+ *
+ * Conventions
+ *   - Every call returns md_status: MD_OK (0) or a negative error code.
+ *     md_last_error(ctx) gives a message for the last failure.
+ *   - Per-particle caller arrays are in the caller's particle order
+ *     ("original id" order); vectors are [Ntot][3] row-major.
+ *   - Pointers documented as DEVICE must be HIP device memory (e.g. torch
+ *     CUDA tensors on ROCm); HOST pointers are ordinary process memory.
+ *     Arrays are borrowed for the duration of the call only.
+ *   - All device work is enqueued on the hip stream given to md_init.
+ *     Calls that return data to the host synchronise that stream and report
+ *     device-side errors latched since the last such call.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - The library allocates its own device buffers with hipMalloc in
+ *     md_init / md_build_cells and frees them in md_destroy.
+ */
+#ifndef MD_H
+#define MD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_ctx_s* md_ctx;
+typedef int32_t md_status;
+
+enum {
+  MD_OK = 0,
+  MD_EINVAL = -1,     /* invalid argument (shape, range, non-finite input) */
+  MD_ENOMEM = -2,     /* device allocation failed */
+  MD_EBOX = -3,       /* box side L < 2 (max rc + skin) */
+  MD_EOVERFLOW = -4,  /* neighbour capacity exceeded; capacity has been grown,
+                         state must be set again (md_set_state) */
+  MD_ENONFINITE = -5, /* a non-finite force or a particle that left the box by
+                         more than one box length between rebuilds */
+  MD_EHIP = -6,       /* a HIP runtime call failed */
+  MD_ESTATE = -7      /* call order (e.g. md_forces before md_set_state) */
+};
+
+enum { MD_POT_LJ = 0, MD_POT_SOFT = 1 };
+enum { MD_TRUNC_SHIFTED_FORCE = 0, MD_TRUNC_SHIFT = 1 };
+enum { MD_FP64 = 0, MD_MIXED = 1 };
+#define MD_MAXT 4
+
+/* Physical and numerical parameters, shared by all replicas of a context. */
+typedef struct {
+  int32_t ntypes;     /* number of species, 1..4 */
+  int32_t potential;  /* MD_POT_LJ: Eq. (1); MD_POT_SOFT: Eq. (2) */
+  int32_t trunc;      /* MD_TRUNC_SHIFTED_FORCE: Eq. (3); MD_TRUNC_SHIFT: V(r)-V(rc) */
+  int32_t precision;  /* MD_FP64: all FP64.  MD_MIXED: pair forces in FP32 with
+                         FP32 accumulation from an FP64 displacement; positions,
+                         velocities, the skin check and energy/virial totals FP64 */
+  double eps[16];     /* eps[a*4+b], symmetric, a,b < ntypes */
+  double sig[16];     /* sigma[a*4+b], symmetric, > 0 */
+  double rc[16];      /* cutoff per species pair, > 0 */
+  double mass[4];     /* mass per species, > 0 */
+  double skin;        /* neighbour-list skin >= 0 (0 rebuilds every step) */
+  double dt;          /* time step */
+  int32_t max_neighbors; /* neighbour capacity per particle; 0 = from density */
+  int32_t graph_steps;   /* steps per captured hipGraph in md_step; 0 = direct */
+  int32_t tpp;           /* lanes per particle in the force kernel (1,2,4,8); 0 = auto */
+  int32_t reserved;
+} md_params;
+
+/* Per-replica observables after the last completed step. */
+typedef struct {
+  double ke;        /* kinetic energy 1/2 sum m v^2 (after any rescale) */
+  double pe;        /* potential energy sum over pairs of V*(r) */
+  double virial;    /* W = sum over pairs of r f(r), f = -d(V*)/dr */
+  double T;         /* 2 ke / (3 n - 3) */
+  double P;         /* (2 ke + W) / (3 V) */
+  double E;         /* ke + pe */
+  double max_disp;  /* largest displacement since the last list build */
+  double T_target;  /* thermostat target of the step (0 for NVE) */
+  int64_t step;     /* steps taken since md_set_state */
+  int64_t n_rebuild;/* list builds since md_set_state */
+} md_obs;
+
+/* Create a context for nrep replicas: n [nrep] particles (HOST, each >= 2),
+ * L [nrep] cubic box sides (HOST).  hip_stream: a hipStream_t (NULL = the
+ * null stream).  Fails with MD_EBOX if some L < 2 (max rc + skin).
+ * The total particle count must be below 2^26 (list entries carry a 26-bit
+ * index and a 6-bit periodic-image code). */
+md_status md_init(md_ctx* out, const md_params* p, int32_t nrep,
+                  const int64_t* n, const double* L, void* hip_stream);
+
+/* Release every device buffer; ctx becomes invalid.  NULL is a no-op. */
+md_status md_destroy(md_ctx ctx);
+
+/* Message for the last failure on ctx (ctx = NULL: last md_init failure). */
+const char* md_last_error(md_ctx ctx);
+
+/* Upload a state (DEVICE pointers, original id order): x, v [Ntot][3]
+ * doubles, type [Ntot] int32 in [0, ntypes).  Positions must lie in
+ * [-L, 2L) per coordinate.  Resets step and rebuild counters and image
+ * counters; the next md_build_cells / md_forces / md_step rebuilds.
+ * Invalid types or non-finite values are reported by this call (it
+ * synchronises). */
+md_status md_set_state(md_ctx ctx, const double* x, const double* v,
+                       const int32_t* type);
+
+/* Download the state (DEVICE pointers, original id order, any may be NULL):
+ * x [Ntot][3] positions as stored (wrapped at the last list build and
+ * drifted since), v [Ntot][3], img [Ntot][3] int32 periodic image counters
+ * (unwrapped position = x + img * L).  Synchronises. */
+md_status md_get_state(md_ctx ctx, double* x, double* v, int32_t* img);
+
+/* Wrap positions into [0, L), bin them into cells of side L/nc with
+ * nc = floor(L / (max rc + skin)) (nc < 3 -> one cell), order particles by
+ * (cell, original id) and build the full neighbour list: j is listed for i
+ * iff r_ij^2 < (rc_ab + skin)^2 over the 27-cell stencil.  Synchronises;
+ * grows the capacity and rebuilds once if it overflowed. */
+md_status md_build_cells(md_ctx ctx);
+
+/* Evaluate forces, potential energy and virial on the current state
+ * (building the list first when needed).  Asynchronous. */
+md_status md_forces(md_ctx ctx);
+
+/* Copy the forces (DEVICE pointer, original id order, [Ntot][3]) as
+ * doubles (MD_FP64) or floats (MD_MIXED).  Synchronises. */
+md_status md_get_forces(md_ctx ctx, void* F);
+
+/* Advance every replica by nsteps velocity-Verlet steps of length dt.
+ * T0, T1: HOST [nrep] thermostat targets or NULL for NVE; the k-th step of
+ * this call (k = 1..nsteps) rescales velocities to
+ * T_target = T0 + (T1 - T0) min(k / ramp_steps, 1)  (ramp_steps <= 0: T0).
+ * log: HOST [nsteps / log_every][nrep] observables of every log_every-th
+ * step, or NULL.  Synchronises at the end and reports latched errors. */
+md_status md_step(md_ctx ctx, int32_t nsteps, const double* T0,
+                  const double* T1, int64_t ramp_steps, md_obs* log,
+                  int32_t log_every);
+
+/* Observables of every replica (HOST [nrep]).  Synchronises. */
+md_status md_observables(md_ctx ctx, md_obs* out);
+
+/* Parity hook, HOST pointers: cell_start [nc^3 + 1] (offsets local to the
+ * replica) and order_ids [n] (replica-local original ids in cell order) of
+ * replica rep as built by the last list build.  Synchronises. */
+md_status md_get_cells(md_ctx ctx, int32_t rep, int32_t* cell_start,
+                       int32_t* order_ids);
+
+/* Parity hook, HOST pointers: for each particle of replica rep (local
+ * original id order) count [n] and up to cap neighbour ids [n][cap]
+ * (replica-local original ids, list order unspecified).  Synchronises. */
+md_status md_get_neighbors(md_ctx ctx, int32_t rep, int32_t* count,
+                           int32_t* ids, int32_t cap);
+
+/* Geometry of replica rep: cells per side, 1/cell side, particle count and
+ * offset, and the neighbour capacity in use. */
+md_status md_replica_info(md_ctx ctx, int32_t rep, int32_t* nc, double* inv_cell,
+                          int64_t* n, int64_t* offset, int32_t* max_neighbors);
+
+/* Kernel timing (not part of the method; for roofline measurement).
+ * md_profile(ctx, every): from now on, in md_step the force kernel launch of
+ * every `every`-th step (0 = off) is bracketed by two hipEvents recorded on
+ * the context stream; earlier records are discarded.
+ * md_profile_read: synchronises and returns the number of bracketed force
+ * launches and their summed duration in milliseconds. */
+typedef struct {
+  int64_t force_launches;
+  double force_ms;
+} md_prof;
+md_status md_profile(md_ctx ctx, int32_t every);
+md_status md_profile_read(md_ctx ctx, md_prof* out);
+
+/* Neighbour-list statistics of replica rep (rep = -1: all replicas) at the
+ * last list build: mean and maximum entries per particle.  Synchronises. */
+md_status md_list_stats(md_ctx ctx, int32_t rep, double* mean, int32_t* max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MD_H */

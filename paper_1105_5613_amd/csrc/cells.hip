@@ -1,0 +1,363 @@
+// cells.hip -- state upload/download, periodic wrap + cell binning, and the
+// stable counting sort of particles by (cell, original id).
+//
+// The cell grid follows the paper's cubic cells of side >= cutoff holding
+// any number of particles (Fig. 1; "Grid-search method").  The doubly linked
+// per-cell particle lists of the paper become, on the GPU, a counting sort:
+// an atomic histogram per cell, an exclusive scan into cell_start, a scatter
+// to the cell segments, and a per-cell rank sort by original id that makes
+// the order deterministic, followed by a gather of the particle records into
+// the new order.
+#include "md_internal.h"
+
+namespace mdk {
+namespace {
+
+__device__ inline void latch(DevState* st, int32_t bits) { atomicOr(&st->err, bits); }
+
+__global__ void k_set_state(int32_t ntot, int32_t stride, const double* __restrict__ x,
+                            const double* __restrict__ v, const int32_t* __restrict__ type,
+                            int32_t ntypes, double4* __restrict__ pos, double* __restrict__ vel,
+                            int32_t* __restrict__ id, int32_t* __restrict__ img, DevState* st) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  int32_t t = type[i];
+  double x0 = x[3 * (size_t)i], x1 = x[3 * (size_t)i + 1], x2 = x[3 * (size_t)i + 2];
+  double v0 = v[3 * (size_t)i], v1 = v[3 * (size_t)i + 1], v2 = v[3 * (size_t)i + 2];
+  if (t < 0 || t >= ntypes) {
+    latch(st, kErrType);
+    t = 0;
+  }
+  if (!isfinite(x0 + x1 + x2 + v0 + v1 + v2)) latch(st, kErrNonFinite);
+  pos[i] = make_double4(x0, x1, x2, (double)t);
+  vel[i] = v0;
+  vel[stride + i] = v1;
+  vel[2 * (size_t)stride + i] = v2;
+  id[i] = i;
+  img[3 * (size_t)i] = 0;
+  img[3 * (size_t)i + 1] = 0;
+  img[3 * (size_t)i + 2] = 0;
+}
+
+__global__ void k_get_state(int32_t ntot, int32_t stride, const double4* __restrict__ pos,
+                            const double* __restrict__ vel, const int32_t* __restrict__ id,
+                            double* __restrict__ x, double* __restrict__ v) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  size_t o = 3 * (size_t)id[i];
+  if (x) {
+    double4 p = pos[i];
+    x[o] = p.x;
+    x[o + 1] = p.y;
+    x[o + 2] = p.z;
+  }
+  if (v) {
+    v[o] = vel[i];
+    v[o + 1] = vel[stride + i];
+    v[o + 2] = vel[2 * (size_t)stride + i];
+  }
+}
+
+template <typename FT>
+__global__ void k_get_forces(int32_t ntot, int32_t stride, const FT* __restrict__ frc,
+                             const int32_t* __restrict__ id, FT* __restrict__ F) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  size_t o = 3 * (size_t)id[i];
+  F[o] = frc[i];
+  F[o + 1] = frc[stride + i];
+  F[o + 2] = frc[2 * (size_t)stride + i];
+}
+
+__global__ void k_mark_rebuild(int32_t nrep, int32_t* rebuild, DevState* st) {
+  int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrep) rebuild[r] = 1;
+  if (r == 0) st->any_rebuild = 1;
+}
+
+__global__ void k_zero_counts(int32_t ncells, const int32_t* __restrict__ cell_rep,
+                              const int32_t* __restrict__ rebuild, const DevState* st,
+                              int32_t* __restrict__ counts) {
+  if (!st->any_rebuild) return;
+  int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncells && rebuild[cell_rep[c]]) counts[c] = 0;
+}
+
+// One periodic wrap (enough between list builds, where every particle moved
+// less than skin/2); x == L after rounding maps to 0 in the next image.
+__device__ inline int32_t wrap1(double& c, double L, int32_t& bad) {
+  int32_t d = 0;
+  if (c < 0.0) {
+    c += L;
+    d = -1;
+  } else if (c >= L) {
+    c -= L;
+    d = 1;
+  }
+  if (c == L) {
+    c = 0.0;
+    d += 1;
+  }
+  if (!(c >= 0.0 && c < L)) {
+    bad = 1;
+    c = 0.0;
+  }
+  return d;
+}
+
+__device__ inline int32_t cell_coord(double c, double inv_cell, int32_t nc) {
+  int32_t q = (int32_t)(c * inv_cell);
+  return q > nc - 1 ? nc - 1 : q;
+}
+
+__global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
+                                               const RepDesc* __restrict__ reps,
+                                               const int32_t* __restrict__ rebuild,
+                                               double4* __restrict__ pos,
+                                               const int32_t* __restrict__ id,
+                                               int32_t* __restrict__ img,
+                                               int32_t* __restrict__ counts,
+                                               int32_t* __restrict__ cell_of,
+                                               int32_t* __restrict__ slot, DevState* st) {
+  const Tile t = tiles[blockIdx.x];
+  if (!rebuild[t.rep]) return;
+  const int32_t i = t.start + threadIdx.x;
+  if (i >= t.end) return;
+  const RepDesc R = reps[t.rep];
+  double4 p = pos[i];
+  int32_t bad = 0;
+  int32_t dx = wrap1(p.x, R.L, bad);
+  int32_t dy = wrap1(p.y, R.L, bad);
+  int32_t dz = wrap1(p.z, R.L, bad);
+  if (bad) latch(st, kErrStray);
+  if (dx | dy | dz) {
+    size_t o = 3 * (size_t)id[i];
+    img[o] += dx;
+    img[o + 1] += dy;
+    img[o + 2] += dz;
+  }
+  pos[i] = p;
+  int32_t qx = cell_coord(p.x, R.inv_cell, R.nc);
+  int32_t qy = cell_coord(p.y, R.inv_cell, R.nc);
+  int32_t qz = cell_coord(p.z, R.inv_cell, R.nc);
+  int32_t c = R.coff + (qz * R.nc + qy) * R.nc + qx;
+  cell_of[i] = c;
+  slot[i] = atomicAdd(&counts[c], 1);
+}
+
+// ---- exclusive scan of the cell counts ------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanBlock = kScanThreads * kScanPer;
+
+__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* total) {
+  __shared__ int32_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    if (k < w) base += wsum[k];
+    tot += wsum[k];
+  }
+  *total = tot;
+  return base + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t* __restrict__ in,
+                                                              int32_t* __restrict__ out,
+                                                              int32_t* __restrict__ bsum,
+                                                              int32_t n, const DevState* st) {
+  if (!st->any_rebuild) return;
+  const int32_t base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+  int32_t loc[kScanPer];
+  int32_t s = 0;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) {
+    int32_t v = (base + e < n) ? in[base + e] : 0;
+    loc[e] = s;
+    s += v;
+  }
+  int32_t tot;
+  int32_t pre = block_exclusive_scan(s, &tot);
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e)
+    if (base + e < n) out[base + e] = pre + loc[e];
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ bsum, int32_t nb,
+                                                   const DevState* st) {
+  if (!st->any_rebuild) return;
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t carry_s;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int32_t c0 = 0; c0 < nb; c0 += 1024) {
+    int32_t k = c0 + threadIdx.x;
+    int32_t v = k < nb ? bsum[k] : 0;
+    int32_t x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+      int32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int32_t base = carry_s, tot = 0;
+    for (int q = 0; q < 16; ++q) {
+      if (q < w) base += wsum[q];
+      tot += wsum[q];
+    }
+    if (k < nb) bsum[k] = base + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry_s;
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, const int32_t* __restrict__ bsum,
+                           int32_t n, int32_t nb, const DevState* st) {
+  if (!st->any_rebuild) return;
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += bsum[i / kScanBlock];
+  else if (i == n) out[n] = bsum[nb];
+}
+
+__global__ __launch_bounds__(kTile) void k_scatter(const Tile* __restrict__ tiles,
+                                                   const int32_t* __restrict__ rebuild,
+                                                   const int32_t* __restrict__ cell_of,
+                                                   const int32_t* __restrict__ slot,
+                                                   const int32_t* __restrict__ cell_start,
+                                                   int32_t* __restrict__ tmp_src) {
+  const Tile t = tiles[blockIdx.x];
+  if (!rebuild[t.rep]) return;
+  const int32_t i = t.start + threadIdx.x;
+  if (i >= t.end) return;
+  tmp_src[cell_start[cell_of[i]] + slot[i]] = i;
+}
+
+// One wave per cell: rank the cell's particles by original id (ids are
+// unique) and gather their records to cell_start + rank.
+__global__ __launch_bounds__(256) void k_cell_gather(
+    int32_t ncells, const int32_t* __restrict__ cell_rep, const int32_t* __restrict__ rebuild,
+    const int32_t* __restrict__ cell_start, const int32_t* __restrict__ tmp_src, int32_t stride,
+    const int32_t* __restrict__ id, const double4* __restrict__ pos,
+    const double* __restrict__ vel, int32_t* __restrict__ id_tmp, double4* __restrict__ pos_tmp,
+    double* __restrict__ vel_tmp) {
+  const int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= ncells) return;
+  if (!rebuild[cell_rep[c]]) return;
+  const int32_t s = cell_start[c], n = cell_start[c + 1] - s;
+  if (n <= 64) {
+    int32_t src = 0, myid = 0x7fffffff;
+    if (lane < n) {
+      src = tmp_src[s + lane];
+      myid = id[src];
+    }
+    int32_t rank = 0;
+    for (int m = 0; m < n; ++m) {
+      int32_t o = __shfl(myid, m, 64);
+      rank += (o < myid) ? 1 : 0;
+    }
+    if (lane < n) {
+      int32_t d = s + rank;
+      id_tmp[d] = myid;
+      pos_tmp[d] = pos[src];
+      vel_tmp[d] = vel[src];
+      vel_tmp[stride + d] = vel[stride + src];
+      vel_tmp[2 * (size_t)stride + d] = vel[2 * (size_t)stride + src];
+    }
+  } else {
+    // crowded cell: quadratic rank straight from memory
+    for (int32_t k = lane; k < n; k += 64) {
+      int32_t src = tmp_src[s + k];
+      int32_t myid = id[src];
+      int32_t rank = 0;
+      for (int32_t m = 0; m < n; ++m) rank += (id[tmp_src[s + m]] < myid) ? 1 : 0;
+      int32_t d = s + rank;
+      id_tmp[d] = myid;
+      pos_tmp[d] = pos[src];
+      vel_tmp[d] = vel[src];
+      vel_tmp[stride + d] = vel[stride + src];
+      vel_tmp[2 * (size_t)stride + d] = vel[2 * (size_t)stride + src];
+    }
+  }
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_set_state(hipStream_t s, int32_t ntot, int32_t stride, const double* x,
+                      const double* v, const int32_t* type, int32_t ntypes, double4* pos,
+                      double* vel, int32_t* id, int32_t* img, DevState* st) {
+  k_set_state<<<nblk(ntot, 256), 256, 0, s>>>(ntot, stride, x, v, type, ntypes, pos, vel, id,
+                                              img, st);
+}
+
+void launch_get_state(hipStream_t s, int32_t ntot, int32_t stride, const double4* pos,
+                      const double* vel, const int32_t* id, double* x, double* v) {
+  k_get_state<<<nblk(ntot, 256), 256, 0, s>>>(ntot, stride, pos, vel, id, x, v);
+}
+
+void launch_get_forces(hipStream_t s, int32_t ntot, int32_t stride, const void* frc,
+                       int32_t mixed, const int32_t* id, void* F) {
+  if (mixed)
+    k_get_forces<float><<<nblk(ntot, 256), 256, 0, s>>>(ntot, stride, (const float*)frc, id,
+                                                       (float*)F);
+  else
+    k_get_forces<double><<<nblk(ntot, 256), 256, 0, s>>>(ntot, stride, (const double*)frc, id,
+                                                        (double*)F);
+}
+
+void launch_mark_rebuild(hipStream_t s, int32_t nrep, int32_t* rebuild, DevState* st) {
+  k_mark_rebuild<<<nblk(nrep, 256), 256, 0, s>>>(nrep, rebuild, st);
+}
+
+void launch_zero_counts(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
+                        const int32_t* rebuild, const DevState* st, int32_t* counts) {
+  k_zero_counts<<<nblk(ncells, 256), 256, 0, s>>>(ncells, cell_rep, rebuild, st, counts);
+}
+
+void launch_bin(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
+                const int32_t* rebuild, double4* pos, const int32_t* id, int32_t* img,
+                int32_t* counts, int32_t* cell_of, int32_t* slot, DevState* st) {
+  k_bin<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, pos, id, img, counts, cell_of, slot, st);
+}
+
+size_t scan_bsum_elems(int32_t ncells) { return (size_t)nblk(ncells, kScanBlock) + 1; }
+
+void launch_scan(hipStream_t s, int32_t ncells, const int32_t* counts, int32_t* cell_start,
+                 int32_t* bsum, const DevState* st) {
+  int32_t nb = (int32_t)nblk(ncells, kScanBlock);
+  k_scan_blocks<<<nb, kScanThreads, 0, s>>>(counts, cell_start, bsum, ncells, st);
+  k_scan_top<<<1, 1024, 0, s>>>(bsum, nb, st);
+  k_scan_add<<<nblk(ncells + 1, 256), 256, 0, s>>>(cell_start, bsum, ncells, nb, st);
+}
+
+void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int32_t* rebuild,
+                    const int32_t* cell_of, const int32_t* slot, const int32_t* cell_start,
+                    int32_t* tmp_src) {
+  k_scatter<<<ntiles, kTile, 0, s>>>(tiles, rebuild, cell_of, slot, cell_start, tmp_src);
+}
+
+void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
+                        const int32_t* rebuild, const int32_t* cell_start,
+                        const int32_t* tmp_src, int32_t stride, const int32_t* id,
+                        const double4* pos, const double* vel, int32_t* id_tmp,
+                        double4* pos_tmp, double* vel_tmp) {
+  k_cell_gather<<<nblk(ncells, 4), 256, 0, s>>>(ncells, cell_rep, rebuild, cell_start, tmp_src,
+                                                stride, id, pos, vel, id_tmp, pos_tmp, vel_tmp);
+}
+
+}  // namespace mdk

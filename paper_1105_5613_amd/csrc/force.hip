@@ -1,0 +1,241 @@
+// force.hip -- the pair-force hot spot: truncated shifted-force pair
+// potential (Eq. (1)/(2) with the shifted-force form Eq. (3)) summed over the
+// full neighbour list, with per-particle potential energy and virial halves
+// reduced to per-tile FP64 partials.
+//
+// FP64 form: everything in double; 1/r from an FP32 reciprocal-square-root
+// seed refined by two Newton-Raphson steps y <- y (3 - r^2 y^2) / 2, the
+// scheme the paper uses on BlueGene/P ("BlueGene specific optimizations").
+// Mixed form: the displacement is formed in FP64 from the FP64 positions,
+// then rounded to FP32; pair arithmetic and the per-particle force sum are
+// FP32; per-particle energy/virial are widened to FP64 for the reductions.
+//
+// One thread per particle (tpp = 1) walks its ELL row; threads per particle
+// tpp in {2, 4, 8} split the row into interleaved slots and combine their
+// partial sums with cross-lane shuffles.
+#include "md_internal.h"
+
+namespace mdk {
+namespace {
+
+__device__ inline double rsqrt_nr(double r2) {
+  double y = (double)__builtin_amdgcn_rsqf((float)r2);
+  const double h = 0.5 * r2;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
+
+template <typename T>
+struct PairLds {
+  T rc2[16], sig2[16], c12[16], c6[16], f12[16], f6[16], vc[16], fs[16], rc[16];
+};
+
+template <typename T>
+__device__ inline void load_pair(PairLds<T>& s, const PairTab* __restrict__ tab) {
+  const int k = threadIdx.x;
+  if (k < 16) {
+    s.rc2[k] = (T)tab->rc2[k];
+    s.sig2[k] = (T)tab->sig2[k];
+    s.c12[k] = (T)tab->c12[k];
+    s.c6[k] = (T)tab->c6[k];
+    s.f12[k] = (T)tab->f12[k];
+    s.f6[k] = (T)tab->f6[k];
+    s.vc[k] = (T)tab->vc[k];
+    s.fs[k] = (T)tab->fs[k];
+    s.rc[k] = (T)tab->rc[k];
+  }
+}
+
+__device__ inline int32_t decode_shift(uint32_t e, int lsb) {
+  // two-bit two's-complement field at bit lsb of e
+  return ((int32_t)(e << (30 - lsb))) >> 30;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Deterministic block sum of three values; result valid in thread 0.
+__device__ inline void block_sum3(double& a, double& b, double& c) {
+  __shared__ double red[3][kTile / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+    red[2][w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = red[0][0];
+    b = red[1][0];
+    c = red[2][0];
+    for (int k = 1; k < kTile / 64; ++k) {
+      a += red[0][k];
+      b += red[1][k];
+      c += red[2][k];
+    }
+  }
+}
+
+template <bool MIXED, int MODE, int TPP>
+__global__ __launch_bounds__(kTile) void k_force(
+    const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
+    const PairTab* __restrict__ tab, const double4* __restrict__ pos, double* __restrict__ vel,
+    void* __restrict__ frc_, const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncount,
+    int32_t stride, int32_t cap, double dt, double* __restrict__ part, DevState* st) {
+  using T = typename std::conditional<MIXED, float, double>::type;
+  __shared__ PairLds<T> P;
+  __shared__ double s_mass[4];
+  load_pair<T>(P, tab);
+  if (threadIdx.x < 4) s_mass[threadIdx.x] = tab->mass[threadIdx.x];
+  __syncthreads();
+
+  // with TPP lanes per particle a block covers kTile / TPP particles; a tile
+  // of kTile particles takes TPP consecutive blocks
+  const int32_t tile_id = blockIdx.x / TPP;
+  const int32_t sub = blockIdx.x % TPP;
+  const Tile t = tiles[tile_id];
+  const double L = reps[t.rep].L;
+  const int32_t lane_p = threadIdx.x % TPP;
+  const int32_t i = t.start + sub * (kTile / TPP) + threadIdx.x / TPP;
+  const bool active = i < t.end;
+
+  double pe = 0.0, w = 0.0, ke = 0.0;
+  T fx = 0, fy = 0, fz = 0;
+  T pe_i = 0, w_i = 0;
+  double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+  int32_t ti = 0;
+  if (active) {
+    p = pos[i];
+    ti = (int32_t)p.w;
+    int32_t n = ncount[i];
+    n = n < cap ? n : cap;
+    const uint32_t* row = nbr + i;
+    for (int32_t k = lane_p; k < n; k += TPP) {
+      const uint32_t e = row[(size_t)k * stride];
+      const double4 q = pos[e & kIdxMask];
+      double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+      if (e >> kIdxBits) {
+        // x_i - (x_j + s L)
+        dx -= (double)decode_shift(e, 26) * L;
+        dy -= (double)decode_shift(e, 28) * L;
+        dz -= (double)decode_shift(e, 30) * L;
+      }
+      const int32_t ab = ti * 4 + (int32_t)q.w;
+      const T ddx = (T)dx, ddy = (T)dy, ddz = (T)dz;
+      const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+      if (r2 < P.rc2[ab]) {
+        T rinv;
+        if constexpr (MIXED)
+          rinv = __builtin_amdgcn_rsqf(r2);
+        else
+          rinv = rsqrt_nr(r2);
+        const T r2inv = rinv * rinv;
+        const T sr2 = P.sig2[ab] * r2inv;
+        const T sr6 = sr2 * sr2 * sr2;
+        const T sr12 = sr6 * sr6;
+        const T fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
+        fx += fr * ddx;
+        fy += fr * ddy;
+        fz += fr * ddz;
+        pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] - (r2 * rinv - P.rc[ab]) * P.fs[ab];
+        w_i += fr * r2;
+      }
+    }
+  }
+  if constexpr (TPP > 1) {
+#pragma unroll
+    for (int d = 1; d < TPP; d <<= 1) {
+      fx += __shfl_xor(fx, d, 64);
+      fy += __shfl_xor(fy, d, 64);
+      fz += __shfl_xor(fz, d, 64);
+      pe_i += __shfl_xor(pe_i, d, 64);
+      w_i += __shfl_xor(w_i, d, 64);
+    }
+  }
+  if (active && lane_p == 0) {
+    if (!isfinite((double)(fx + fy + fz))) atomicOr(&st->err, kErrNonFinite);
+    T* frc = (T*)frc_;
+    frc[i] = fx;
+    frc[stride + i] = fy;
+    frc[2 * (size_t)stride + i] = fz;
+    pe = 0.5 * (double)pe_i;
+    w = 0.5 * (double)w_i;
+    const double m = s_mass[ti];
+    double v0 = vel[i], v1 = vel[stride + i], v2 = vel[2 * (size_t)stride + i];
+    if (MODE == 1) {
+      const double hm = 0.5 * dt / m;
+      v0 += hm * (double)fx;
+      v1 += hm * (double)fy;
+      v2 += hm * (double)fz;
+      vel[i] = v0;
+      vel[stride + i] = v1;
+      vel[2 * (size_t)stride + i] = v2;
+    }
+    ke = 0.5 * m * (v0 * v0 + v1 * v1 + v2 * v2);
+  }
+  block_sum3(pe, w, ke);
+  if (threadIdx.x == 0) {
+    double* o = part + 4 * (size_t)blockIdx.x;
+    o[0] = pe;
+    o[1] = w;
+    o[2] = ke;
+  }
+}
+
+template <bool MIXED, int MODE>
+void launch_t(hipStream_t s, int32_t tpp, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
+              const PairTab* tab, const double4* pos, double* vel, void* frc,
+              const uint32_t* nbr, const int32_t* ncount, int32_t stride, int32_t cap, double dt,
+              double* part, DevState* st) {
+  switch (tpp) {
+    case 2:
+      k_force<MIXED, MODE, 2><<<ntiles * 2, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, nbr,
+                                                           ncount, stride, cap, dt, part, st);
+      break;
+    case 4:
+      k_force<MIXED, MODE, 4><<<ntiles * 4, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, nbr,
+                                                           ncount, stride, cap, dt, part, st);
+      break;
+    case 8:
+      k_force<MIXED, MODE, 8><<<ntiles * 8, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, nbr,
+                                                           ncount, stride, cap, dt, part, st);
+      break;
+    default:
+      k_force<MIXED, MODE, 1><<<ntiles, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, nbr,
+                                                       ncount, stride, cap, dt, part, st);
+  }
+}
+
+}  // namespace
+
+// Partials: one FP64 triple (pe, w, ke) per launched block; with tpp lanes
+// per particle, tile t owns blocks [t*tpp, (t+1)*tpp).
+void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t ntiles,
+                  const Tile* tiles, const RepDesc* reps, const PairTab* tab, const double4* pos,
+                  double* vel, void* frc, const uint32_t* nbr, const int32_t* ncount,
+                  int32_t stride, int32_t cap, double dt, double* part, DevState* st) {
+  if (mixed) {
+    if (mode)
+      launch_t<true, 1>(s, tpp, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride, cap,
+                        dt, part, st);
+    else
+      launch_t<true, 0>(s, tpp, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride, cap,
+                        dt, part, st);
+  } else {
+    if (mode)
+      launch_t<false, 1>(s, tpp, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride,
+                         cap, dt, part, st);
+    else
+      launch_t<false, 0>(s, tpp, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride,
+                         cap, dt, part, st);
+  }
+}
+
+}  // namespace mdk

@@ -1,0 +1,232 @@
+// integrate.hip -- velocity-Verlet kick/drift with the skin check, and the
+// per-replica reductions, observables and isokinetic thermostat.
+//
+// Velocity Verlet ("Parallel force calculation"): v += dt/2 F/m; x += dt v;
+// forces; v += dt/2 F/m.  The second half kick runs inside the force kernel;
+// this file holds the first half kick and the drift, fused with the
+// displacement test |x - x_ref|^2 > (skin/2)^2 that schedules list rebuilds
+// and with the pending thermostat factor of the previous step.
+//
+// Canonical runs (fixed T, "BBMD scaling results"; the glass-section T ramp)
+// rescale v by lambda = sqrt(T_target / T_inst) after the second half kick,
+// with T_inst = 2 KE / (3 n - 3).  lambda is computed by the reduction and
+// applied at the start of the next kick (or by apply_lambda at the end of a
+// call), which is the same arithmetic as rescaling right away.
+#include "md_internal.h"
+
+namespace mdk {
+namespace {
+
+template <typename FT, bool THERMO>
+__global__ __launch_bounds__(kTile) void k_kick_drift(
+    const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
+    const PairTab* __restrict__ tab, double4* __restrict__ pos, double* __restrict__ vel,
+    const FT* __restrict__ frc, const double* __restrict__ xref, int32_t stride, double dt,
+    const double* __restrict__ lam, int32_t* __restrict__ rebuild,
+    unsigned long long* __restrict__ maxd2, DevState* st) {
+  __shared__ double s_im[4];
+  __shared__ double s_red[kTile / 64];
+  if (threadIdx.x < 4) s_im[threadIdx.x] = tab->inv_mass[threadIdx.x];
+  __syncthreads();
+  const Tile t = tiles[blockIdx.x];
+  const int32_t i = t.start + threadIdx.x;
+  double d2 = 0.0;
+  if (i < t.end) {
+    double4 p = pos[i];
+    const double hm = 0.5 * dt * s_im[(int32_t)p.w];
+    double v0 = vel[i], v1 = vel[stride + i], v2 = vel[2 * (size_t)stride + i];
+    if (THERMO) {
+      const double l = lam[t.rep];
+      v0 *= l;
+      v1 *= l;
+      v2 *= l;
+    }
+    v0 += hm * (double)frc[i];
+    v1 += hm * (double)frc[stride + i];
+    v2 += hm * (double)frc[2 * (size_t)stride + i];
+    p.x += dt * v0;
+    p.y += dt * v1;
+    p.z += dt * v2;
+    pos[i] = p;
+    vel[i] = v0;
+    vel[stride + i] = v1;
+    vel[2 * (size_t)stride + i] = v2;
+    const double e0 = p.x - xref[i], e1 = p.y - xref[stride + i],
+                 e2 = p.z - xref[2 * (size_t)stride + i];
+    d2 = e0 * e0 + e1 * e1 + e2 * e2;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) d2 = fmax(d2, __shfl_xor(d2, d, 64));
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = s_red[0];
+    for (int k = 1; k < kTile / 64; ++k) m = fmax(m, s_red[k]);
+    const RepDesc& R = reps[t.rep];
+    if (m > R.half_skin2) {
+      rebuild[t.rep] = 1;
+      st->any_rebuild = 1;
+    }
+    // non-negative doubles order like their bit patterns
+    atomicMax(&maxd2[t.rep], (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__device__ inline void neumaier(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x))
+    c += (s - t) + x;
+  else
+    c += (x - t) + s;
+  s = t;
+}
+
+// One block per replica: compensated sums of the per-block partials in a
+// fixed order (deterministic), then observables and the thermostat factor.
+__global__ __launch_bounds__(256) void k_reduce(const RepDesc* __restrict__ reps,
+                                                const double* __restrict__ part, int32_t tpp,
+                                                int32_t step, ThermoArgs ta,
+                                                int64_t* __restrict__ kcall,
+                                                double* __restrict__ lam,
+                                                int32_t* __restrict__ rebuild,
+                                                unsigned long long* __restrict__ maxd2,
+                                                md_obs* __restrict__ obs, DevState* st) {
+  __shared__ double red[3][256];
+  const int32_t r = blockIdx.x;
+  const RepDesc R = reps[r];
+  double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
+  const int32_t b0 = R.tile0 * tpp, b1 = R.tile1 * tpp;
+  for (int32_t b = b0 + threadIdx.x; b < b1; b += 256)
+    for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double pe = red[0][0], w = red[1][0];
+  double ke = red[2][0];
+  md_obs o = obs[r];
+  o.pe = pe;
+  o.virial = w;
+  o.T_target = 0.0;
+  const double md2 = __longlong_as_double((long long)maxd2[r]);
+  o.max_disp = sqrt(md2);
+  if (step) {
+    const int64_t k = ++kcall[r];
+    if (ta.thermo) {
+      const double t0 = ta.T0[r], t1 = ta.T1[r];
+      double tt = t0;
+      if (ta.ramp > 0) {
+        double f = (double)k / (double)ta.ramp;
+        f = f > 1.0 ? 1.0 : f;
+        tt = t0 + (t1 - t0) * f;
+      }
+      const double ti = 2.0 * ke / R.dof;
+      const double l = sqrt(tt / ti);
+      lam[r] = l;
+      ke = ke * l * l;
+      o.T_target = tt;
+    }
+    o.step += 1;
+    if (rebuild[r]) {
+      o.n_rebuild += 1;
+      rebuild[r] = 0;
+      maxd2[r] = 0ull;
+    }
+    if (r == 0) st->any_rebuild = 0;
+  }
+  o.ke = ke;
+  o.T = 2.0 * ke / R.dof;
+  o.P = (2.0 * ke + w) / (3.0 * R.volume);
+  o.E = ke + pe;
+  obs[r] = o;
+  if (step && ta.log_every > 0) {
+    const int64_t k = kcall[r];
+    if (k % ta.log_every == 0) {
+      const int64_t idx = k / ta.log_every - 1;
+      if (idx >= 0 && idx < ta.nlog) ta.log[idx * gridDim.x + r] = o;
+    }
+  }
+}
+
+__global__ void k_after_build(int32_t nrep, int32_t* rebuild, unsigned long long* maxd2,
+                              md_obs* obs, DevState* st) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrep && rebuild[r]) {
+    obs[r].n_rebuild += 1;
+    rebuild[r] = 0;
+    maxd2[r] = 0ull;
+  }
+  if (r == 0) st->any_rebuild = 0;
+}
+
+__global__ void k_begin_call(int32_t nrep, int64_t* kcall, double* lam) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrep) {
+    kcall[r] = 0;
+    lam[r] = 1.0;
+  }
+}
+
+__global__ __launch_bounds__(kTile) void k_apply_lambda(const Tile* __restrict__ tiles,
+                                                        int32_t stride, double* __restrict__ vel,
+                                                        const double* __restrict__ lam) {
+  const Tile t = tiles[blockIdx.x];
+  const int32_t i = t.start + threadIdx.x;
+  if (i >= t.end) return;
+  const double l = lam[t.rep];
+  vel[i] *= l;
+  vel[stride + i] *= l;
+  vel[2 * (size_t)stride + i] *= l;
+}
+
+__global__ void k_reset_lambda(int32_t nrep, double* lam) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrep) lam[r] = 1.0;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t ntiles,
+                       const Tile* tiles, const RepDesc* reps, const PairTab* tab, double4* pos,
+                       double* vel, const void* frc, const double* xref, int32_t stride,
+                       double dt, const double* lam, int32_t* rebuild, unsigned long long* maxd2,
+                       DevState* st) {
+#define KD(FT, TH)                                                                          \
+  k_kick_drift<FT, TH><<<ntiles, kTile, 0, s>>>(tiles, reps, tab, pos, vel, (const FT*)frc, \
+                                                xref, stride, dt, lam, rebuild, maxd2, st)
+  if (mixed) {
+    if (thermo) KD(float, true); else KD(float, false);
+  } else {
+    if (thermo) KD(double, true); else KD(double, false);
+  }
+#undef KD
+}
+
+void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
+                   int32_t tpp, int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
+                   int32_t* rebuild, unsigned long long* maxd2, md_obs* obs, DevState* st) {
+  k_reduce<<<nrep, 256, 0, s>>>(reps, part, tpp, step, ta, kcall, lam, rebuild, maxd2, obs, st);
+}
+
+void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, unsigned long long* maxd2,
+                        md_obs* obs, DevState* st) {
+  k_after_build<<<nblk(nrep, 256), 256, 0, s>>>(nrep, rebuild, maxd2, obs, st);
+}
+
+void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam) {
+  k_begin_call<<<nblk(nrep, 256), 256, 0, s>>>(nrep, kcall, lam);
+}
+
+void launch_apply_lambda(hipStream_t s, int32_t ntiles, const Tile* tiles, int32_t stride,
+                         double* vel, double* lam, int32_t nrep) {
+  k_apply_lambda<<<ntiles, kTile, 0, s>>>(tiles, stride, vel, lam);
+  k_reset_lambda<<<nblk(nrep, 256), 256, 0, s>>>(nrep, lam);
+}
+
+}  // namespace mdk

@@ -1,0 +1,683 @@
+// md_api.cpp -- the C ABI declared in include/md.h: validation, derived
+// constants, device buffers, the per-step launch sequence and error latch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "md_internal.h"
+
+using namespace mdk;
+
+struct md_ctx_s {
+  md_params p{};
+  int32_t nrep = 0, ntot = 0, stride = 0, ncells = 0, ntiles = 0, cap = 0, tpp = 1;
+  int32_t mixed = 0;
+  hipStream_t stream = nullptr;
+  std::vector<RepDesc> reps_h;
+  std::vector<Tile> tiles_h;
+  // device buffers
+  RepDesc* reps = nullptr;
+  Tile* tiles = nullptr;
+  PairTab* tab = nullptr;
+  DevState* st = nullptr;
+  int32_t *cell_rep = nullptr, *counts = nullptr, *cell_start = nullptr, *bsum = nullptr;
+  int32_t *cell_of = nullptr, *slot = nullptr, *tmp_src = nullptr;
+  double4 *pos = nullptr, *pos_tmp = nullptr;
+  double *vel = nullptr, *vel_tmp = nullptr, *xref = nullptr;
+  void* frc = nullptr;
+  int32_t *id = nullptr, *id_tmp = nullptr, *img = nullptr;
+  uint32_t* nbr = nullptr;
+  int32_t* ncount = nullptr;
+  double* part = nullptr;
+  int32_t* rebuild = nullptr;
+  unsigned long long* maxd2 = nullptr;
+  md_obs* obs = nullptr;
+  int64_t* kcall = nullptr;
+  double* lam = nullptr;
+  double* therm = nullptr;  // T0 [nrep], T1 [nrep]
+  md_obs* log_dev = nullptr;
+  int64_t log_cap = 0;
+  std::vector<void*> owned;
+  // force-kernel timing
+  int32_t prof_every = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  bool has_state = false, built = false, forces_valid = false;
+  std::string err;
+};
+
+namespace {
+
+std::string g_init_error;
+
+md_status fail(md_ctx c, md_status code, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_init_error = msg;
+  return code;
+}
+
+#define HIPCHECK(c, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(c, MD_EHIP, std::string(#call " failed: ") + hipGetErrorString(e_));     \
+  } while (0)
+
+template <typename T>
+md_status dalloc(md_ctx c, T** ptr, size_t count) {
+  void* p = nullptr;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, MD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->owned.push_back(p);
+  *ptr = (T*)p;
+  return MD_OK;
+}
+
+void dfree(md_ctx c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->owned.begin(), c->owned.end(), p);
+  if (it != c->owned.end()) c->owned.erase(it);
+  (void)hipFree(p);
+}
+
+double max_rc(const md_params& p) {
+  double m = 0.0;
+  for (int a = 0; a < p.ntypes; ++a)
+    for (int b = 0; b < p.ntypes; ++b) m = std::max(m, p.rc[a * MD_MAXT + b]);
+  return m;
+}
+
+// Untruncated pair potential (Eq. (1) / Eq. (2)) and dV/dr at r, for the
+// host-side shift constants of Eq. (3).
+void plain_v(const md_params& p, int ab, double r, double* v, double* dv) {
+  double s = p.sig[ab] / r;
+  double s6 = s * s * s * s * s * s, s12 = s6 * s6;
+  double e = p.eps[ab];
+  if (p.potential == MD_POT_SOFT) {
+    *v = 4.0 * e * s12;
+    *dv = -48.0 * e * s12 / r;
+  } else {
+    *v = 4.0 * e * (s12 - s6);
+    *dv = -4.0 * e * (12.0 * s12 - 6.0 * s6) / r;
+  }
+}
+
+md_status validate(const md_params* p, std::string* why) {
+  if (!p) return *why = "params is NULL", MD_EINVAL;
+  if (p->ntypes < 1 || p->ntypes > MD_MAXT) return *why = "ntypes must be 1..4", MD_EINVAL;
+  if (p->potential != MD_POT_LJ && p->potential != MD_POT_SOFT)
+    return *why = "unknown potential", MD_EINVAL;
+  if (p->trunc != MD_TRUNC_SHIFTED_FORCE && p->trunc != MD_TRUNC_SHIFT)
+    return *why = "unknown truncation", MD_EINVAL;
+  if (p->precision != MD_FP64 && p->precision != MD_MIXED)
+    return *why = "unknown precision", MD_EINVAL;
+  for (int a = 0; a < p->ntypes; ++a) {
+    if (!(p->mass[a] > 0.0) || !std::isfinite(p->mass[a])) return *why = "mass must be > 0", MD_EINVAL;
+    for (int b = 0; b < p->ntypes; ++b) {
+      int ab = a * MD_MAXT + b, ba = b * MD_MAXT + a;
+      if (!(p->sig[ab] > 0.0) || !(p->rc[ab] > 0.0) || !std::isfinite(p->eps[ab]) ||
+          !std::isfinite(p->sig[ab]) || !std::isfinite(p->rc[ab]))
+        return *why = "sigma and rc must be finite and > 0", MD_EINVAL;
+      if (p->eps[ab] != p->eps[ba] || p->sig[ab] != p->sig[ba] || p->rc[ab] != p->rc[ba])
+        return *why = "species tables must be symmetric", MD_EINVAL;
+    }
+  }
+  if (!(p->skin >= 0.0) || !std::isfinite(p->skin)) return *why = "skin must be >= 0", MD_EINVAL;
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return *why = "dt must be > 0", MD_EINVAL;
+  if (p->max_neighbors < 0) return *why = "max_neighbors must be >= 0", MD_EINVAL;
+  if (p->tpp != 0 && p->tpp != 1 && p->tpp != 2 && p->tpp != 4 && p->tpp != 8)
+    return *why = "tpp must be 0, 1, 2, 4 or 8", MD_EINVAL;
+  if (p->graph_steps < 0) return *why = "graph_steps must be >= 0", MD_EINVAL;
+  return MD_OK;
+}
+
+md_status sync_and_check(md_ctx c) {
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  DevState st{};
+  HIPCHECK(c, hipMemcpy(&st, c->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  if (st.err) {
+    DevState z{};
+    HIPCHECK(c, hipMemcpy(c->st, &z, sizeof(DevState), hipMemcpyHostToDevice));
+    if (st.err & kErrOverflow)
+      return fail(c, MD_EOVERFLOW, "neighbour list capacity exceeded");
+    if (st.err & kErrType) return fail(c, MD_EINVAL, "species index out of range");
+    if (st.err & kErrStray)
+      return fail(c, MD_ENONFINITE, "a position left the box by more than one box length");
+    return fail(c, MD_ENONFINITE, "non-finite position, velocity or force");
+  }
+  return MD_OK;
+}
+
+void run_chain(md_ctx c) {
+  hipStream_t s = c->stream;
+  launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
+  launch_bin(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->pos, c->id, c->img, c->counts,
+             c->cell_of, c->slot, c->st);
+  launch_scan(s, c->ncells, c->counts, c->cell_start, c->bsum, c->st);
+  launch_scatter(s, c->ntiles, c->tiles, c->rebuild, c->cell_of, c->slot, c->cell_start,
+                 c->tmp_src);
+  launch_cell_gather(s, c->ncells, c->cell_rep, c->rebuild, c->cell_start, c->tmp_src, c->stride,
+                     c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp);
+  launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->p.ntypes, c->cell_start,
+               c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
+               c->xref, c->nbr, c->ncount, c->st);
+}
+
+md_status grow_capacity(md_ctx c) {
+  std::vector<int32_t> cnt(c->ntot);
+  HIPCHECK(c, hipMemcpy(cnt.data(), c->ncount, sizeof(int32_t) * c->ntot, hipMemcpyDeviceToHost));
+  int32_t m = 0;
+  for (int32_t v : cnt) m = std::max(m, v);
+  int32_t cap = ((m + 16 + 7) / 8) * 8;
+  dfree(c, c->nbr);
+  c->nbr = nullptr;
+  md_status rc = dalloc(c, &c->nbr, (size_t)cap * c->stride);
+  if (rc) return rc;
+  c->cap = cap;
+  return MD_OK;
+}
+
+// Full rebuild of every replica (md_build_cells and the first build after
+// md_set_state); grows the neighbour capacity once on overflow.
+md_status build_all(md_ctx c) {
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    launch_mark_rebuild(c->stream, c->nrep, c->rebuild, c->st);
+    run_chain(c);
+    launch_after_build(c->stream, c->nrep, c->rebuild, c->maxd2, c->obs, c->st);
+    md_status rc = sync_and_check(c);
+    if (rc == MD_OK) {
+      c->built = true;
+      c->forces_valid = false;
+      return MD_OK;
+    }
+    if (rc != MD_EOVERFLOW || attempt == 1) return rc;
+    rc = grow_capacity(c);
+    if (rc) return rc;
+  }
+  return MD_OK;
+}
+
+ThermoArgs no_thermo() {
+  ThermoArgs t{};
+  return t;
+}
+
+void launch_forces0(md_ctx c) {
+  launch_force(c->stream, c->mixed, 0, c->tpp, c->ntiles, c->tiles, c->reps, c->tab, c->pos,
+               c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st);
+  launch_reduce(c->stream, c->nrep, c->reps, c->part, c->tpp, 0, no_thermo(), c->kcall, c->lam,
+                c->rebuild, c->maxd2, c->obs, c->st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* md_last_error(md_ctx c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* n,
+                  const double* L, void* hip_stream) {
+  if (!out) return fail(nullptr, MD_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (validate(p, &why)) return fail(nullptr, MD_EINVAL, why);
+  if (nrep < 1 || !n || !L) return fail(nullptr, MD_EINVAL, "need nrep >= 1 and n, L arrays");
+  const double rcmax = max_rc(*p);
+  int64_t ntot = 0;
+  for (int r = 0; r < nrep; ++r) {
+    if (n[r] < 2) return fail(nullptr, MD_EINVAL, "every replica needs at least 2 particles");
+    if (!std::isfinite(L[r]) || !(L[r] >= 2.0 * (rcmax + p->skin)))
+      return fail(nullptr, MD_EBOX, "box side L must be >= 2 (max rc + skin)");
+    ntot += n[r];
+  }
+  if (ntot > (int64_t)kIdxMask + 1)
+    return fail(nullptr, MD_EINVAL, "total particle count must be <= 2^26");
+
+  md_ctx c = new md_ctx_s();
+  c->p = *p;
+  c->nrep = nrep;
+  c->ntot = (int32_t)ntot;
+  c->stride = (int32_t)(((ntot + 63) / 64) * 64);
+  c->mixed = p->precision == MD_MIXED;
+  c->tpp = p->tpp == 0 ? 1 : p->tpp;
+  c->stream = (hipStream_t)hip_stream;
+
+  // replica geometry: cells of side >= max rc + skin (nc < 3 -> one cell)
+  const double side = rcmax + p->skin;
+  int32_t off = 0, coff = 0, tile = 0;
+  double rho_max = 0.0;
+  for (int r = 0; r < nrep; ++r) {
+    RepDesc d{};
+    int32_t nc = (int32_t)std::floor(L[r] / side);
+    if (nc < 3) nc = 1;
+    d.L = L[r];
+    d.inv_cell = (double)nc / L[r];
+    d.half_skin2 = (0.5 * p->skin) * (0.5 * p->skin);
+    d.dof = 3.0 * (double)n[r] - 3.0;
+    d.volume = L[r] * L[r] * L[r];
+    d.off = off;
+    d.n = (int32_t)n[r];
+    d.coff = coff;
+    d.nc = nc;
+    d.tile0 = tile;
+    for (int32_t s0 = off; s0 < off + d.n; s0 += kTile) {
+      Tile t{};
+      t.rep = r;
+      t.start = s0;
+      t.end = std::min(s0 + kTile, off + d.n);
+      c->tiles_h.push_back(t);
+      ++tile;
+    }
+    d.tile1 = tile;
+    c->reps_h.push_back(d);
+    off += d.n;
+    int64_t cells = (int64_t)nc * nc * nc;
+    if ((int64_t)coff + cells > (int64_t)0x7fffffff) {
+      delete c;
+      return fail(nullptr, MD_EINVAL, "too many cells");
+    }
+    coff += (int32_t)cells;
+    rho_max = std::max(rho_max, (double)n[r] / d.volume);
+  }
+  c->ncells = coff;
+  c->ntiles = tile;
+  if (p->max_neighbors > 0) {
+    c->cap = p->max_neighbors;
+  } else {
+    const double expect = rho_max * 4.0 / 3.0 * M_PI * side * side * side;
+    c->cap = (int32_t)(((int64_t)std::ceil(1.5 * expect) + 16 + 7) / 8 * 8);
+  }
+
+  // pair table: shift constants of Eq. (3) computed on the host in FP64
+  PairTab tab{};
+  for (int a = 0; a < MD_MAXT; ++a)
+    for (int b = 0; b < MD_MAXT; ++b) {
+      const int ab = a * MD_MAXT + b;
+      if (a >= p->ntypes || b >= p->ntypes) {
+        tab.rc2[ab] = 0.0;  // never used
+        tab.thr[ab] = 0.0;
+        tab.sig2[ab] = 1.0;
+        continue;
+      }
+      const double rc = p->rc[ab];
+      const double t = rc + p->skin;
+      tab.rc2[ab] = rc * rc;
+      tab.thr[ab] = t * t;
+      tab.sig2[ab] = p->sig[ab] * p->sig[ab];
+      const double e = p->eps[ab];
+      tab.c12[ab] = 4.0 * e;
+      tab.c6[ab] = p->potential == MD_POT_SOFT ? 0.0 : -4.0 * e;
+      tab.f12[ab] = 48.0 * e;
+      tab.f6[ab] = p->potential == MD_POT_SOFT ? 0.0 : -24.0 * e;
+      double vc, dvc;
+      plain_v(*p, ab, rc, &vc, &dvc);
+      tab.vc[ab] = vc;
+      tab.fs[ab] = p->trunc == MD_TRUNC_SHIFTED_FORCE ? dvc : 0.0;
+      tab.rc[ab] = rc;
+    }
+  for (int a = 0; a < MD_MAXT; ++a) {
+    tab.mass[a] = a < p->ntypes ? p->mass[a] : 1.0;
+    tab.inv_mass[a] = 1.0 / tab.mass[a];
+  }
+
+  std::vector<int32_t> cell_rep(c->ncells);
+  for (int r = 0; r < nrep; ++r) {
+    const RepDesc& d = c->reps_h[r];
+    std::fill(cell_rep.begin() + d.coff, cell_rep.begin() + d.coff + d.nc * d.nc * d.nc, r);
+  }
+
+  const size_t N = c->ntot, S = c->stride;
+  md_status rc = MD_OK;
+#define ALLOC(ptr, count)                       \
+  if ((rc = dalloc(c, &(ptr), (count))) != 0) { \
+    std::string m_ = c->err;                    \
+    md_destroy(c);                              \
+    return fail(nullptr, rc, m_);               \
+  }
+  ALLOC(c->reps, (size_t)nrep);
+  ALLOC(c->tiles, (size_t)c->ntiles);
+  ALLOC(c->tab, 1);
+  ALLOC(c->st, 1);
+  ALLOC(c->cell_rep, (size_t)c->ncells);
+  ALLOC(c->counts, (size_t)c->ncells);
+  ALLOC(c->cell_start, (size_t)c->ncells + 1);
+  ALLOC(c->bsum, scan_bsum_elems(c->ncells));
+  ALLOC(c->cell_of, N);
+  ALLOC(c->slot, N);
+  ALLOC(c->tmp_src, N);
+  ALLOC(c->pos, N);
+  ALLOC(c->pos_tmp, N);
+  ALLOC(c->vel, 3 * S);
+  ALLOC(c->vel_tmp, 3 * S);
+  ALLOC(c->xref, 3 * S);
+  if (c->mixed) {
+    float* f = nullptr;
+    ALLOC(f, 3 * S);
+    c->frc = f;
+  } else {
+    double* f = nullptr;
+    ALLOC(f, 3 * S);
+    c->frc = f;
+  }
+  ALLOC(c->id, N);
+  ALLOC(c->id_tmp, N);
+  ALLOC(c->img, 3 * N);
+  ALLOC(c->nbr, (size_t)c->cap * S);
+  ALLOC(c->ncount, N);
+  ALLOC(c->part, 4 * (size_t)c->ntiles * 8);
+  ALLOC(c->rebuild, (size_t)nrep);
+  ALLOC(c->maxd2, (size_t)nrep);
+  ALLOC(c->obs, (size_t)nrep);
+  ALLOC(c->kcall, (size_t)nrep);
+  ALLOC(c->lam, (size_t)nrep);
+  ALLOC(c->therm, 2 * (size_t)nrep);
+#undef ALLOC
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  std::vector<double> ones(nrep, 1.0);
+  bool ok = up(c->reps, c->reps_h.data(), sizeof(RepDesc) * nrep) &&
+            up(c->tiles, c->tiles_h.data(), sizeof(Tile) * c->ntiles) &&
+            up(c->tab, &tab, sizeof(PairTab)) &&
+            up(c->cell_rep, cell_rep.data(), sizeof(int32_t) * c->ncells) &&
+            up(c->lam, ones.data(), sizeof(double) * nrep) &&
+            hipMemset(c->st, 0, sizeof(DevState)) == hipSuccess &&
+            hipMemset(c->counts, 0, sizeof(int32_t) * c->ncells) == hipSuccess &&
+            hipMemset(c->rebuild, 0, sizeof(int32_t) * nrep) == hipSuccess &&
+            hipMemset(c->maxd2, 0, sizeof(unsigned long long) * nrep) == hipSuccess &&
+            hipMemset(c->obs, 0, sizeof(md_obs) * nrep) == hipSuccess &&
+            hipMemset(c->kcall, 0, sizeof(int64_t) * nrep) == hipSuccess &&
+            hipMemset(c->frc, 0, (c->mixed ? 4 : 8) * 3 * S) == hipSuccess;
+  if (!ok) {
+    md_destroy(c);
+    return fail(nullptr, MD_EHIP, "uploading context tables failed");
+  }
+  *out = c;
+  return MD_OK;
+}
+
+md_status md_destroy(md_ctx c) {
+  if (!c) return MD_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (void* p : c->owned) (void)hipFree(p);
+  c->owned.clear();
+  delete c;
+  return MD_OK;
+}
+
+md_status md_set_state(md_ctx c, const double* x, const double* v, const int32_t* type) {
+  if (!c) return MD_EINVAL;
+  if (!x || !v || !type) return fail(c, MD_EINVAL, "x, v and type are required");
+  launch_set_state(c->stream, c->ntot, c->stride, x, v, type, c->p.ntypes, c->pos, c->vel, c->id,
+                   c->img, c->st);
+  HIPCHECK(c, hipMemsetAsync(c->obs, 0, sizeof(md_obs) * c->nrep, c->stream));
+  HIPCHECK(c, hipMemsetAsync(c->maxd2, 0, sizeof(unsigned long long) * c->nrep, c->stream));
+  HIPCHECK(c, hipMemsetAsync(c->frc, 0, (c->mixed ? 4 : 8) * 3 * (size_t)c->stride, c->stream));
+  md_status rc = sync_and_check(c);
+  // positions are checked against the box at the first wrap
+  c->has_state = rc == MD_OK;
+  c->built = false;
+  c->forces_valid = false;
+  return rc;
+}
+
+md_status md_get_state(md_ctx c, double* x, double* v, int32_t* img) {
+  if (!c) return MD_EINVAL;
+  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+  if (x || v) launch_get_state(c->stream, c->ntot, c->stride, c->pos, c->vel, c->id, x, v);
+  if (img)
+    HIPCHECK(c, hipMemcpyAsync(img, c->img, sizeof(int32_t) * 3 * (size_t)c->ntot,
+                               hipMemcpyDeviceToDevice, c->stream));
+  return sync_and_check(c);
+}
+
+md_status md_build_cells(md_ctx c) {
+  if (!c) return MD_EINVAL;
+  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+  return build_all(c);
+}
+
+md_status md_forces(md_ctx c) {
+  if (!c) return MD_EINVAL;
+  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+  if (!c->built) {
+    md_status rc = build_all(c);
+    if (rc) return rc;
+  }
+  launch_forces0(c);
+  c->forces_valid = true;
+  return MD_OK;
+}
+
+md_status md_get_forces(md_ctx c, void* F) {
+  if (!c) return MD_EINVAL;
+  if (!F) return fail(c, MD_EINVAL, "F is NULL");
+  if (!c->forces_valid) return fail(c, MD_ESTATE, "no forces computed");
+  launch_get_forces(c->stream, c->ntot, c->stride, c->frc, c->mixed, c->id, F);
+  return sync_and_check(c);
+}
+
+md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
+                  int64_t ramp_steps, md_obs* log, int32_t log_every) {
+  if (!c) return MD_EINVAL;
+  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+  if (nsteps < 0) return fail(c, MD_EINVAL, "nsteps must be >= 0");
+  if (log && log_every <= 0) return fail(c, MD_EINVAL, "log needs log_every > 0");
+  const int32_t thermo = T0 != nullptr;
+  if (thermo) {
+    for (int r = 0; r < c->nrep; ++r) {
+      const double t1 = T1 ? T1[r] : T0[r];
+      if (!(T0[r] > 0.0) || !(t1 > 0.0) || !std::isfinite(T0[r]) || !std::isfinite(t1))
+        return fail(c, MD_EINVAL, "thermostat targets must be finite and > 0");
+    }
+  }
+  if (!c->built) {
+    md_status rc = build_all(c);
+    if (rc) return rc;
+  }
+  if (!c->forces_valid) {
+    launch_forces0(c);
+    c->forces_valid = true;
+  }
+  ThermoArgs ta{};
+  if (thermo) {
+    std::vector<double> th(2 * c->nrep);
+    for (int r = 0; r < c->nrep; ++r) {
+      th[r] = T0[r];
+      th[c->nrep + r] = T1 ? T1[r] : T0[r];
+    }
+    HIPCHECK(c, hipMemcpyAsync(c->therm, th.data(), sizeof(double) * th.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));  // th is a local buffer
+    ta.T0 = c->therm;
+    ta.T1 = c->therm + c->nrep;
+    ta.ramp = ramp_steps;
+    ta.thermo = 1;
+  }
+  int64_t nlog = 0;
+  if (log) {
+    nlog = nsteps / log_every;
+    if (nlog * c->nrep > c->log_cap) {
+      dfree(c, c->log_dev);
+      c->log_dev = nullptr;
+      c->log_cap = 0;
+      md_status rc = dalloc(c, &c->log_dev, (size_t)std::max<int64_t>(nlog * c->nrep, 1));
+      if (rc) return rc;
+      c->log_cap = nlog * c->nrep;
+    }
+    ta.log_every = log_every;
+    ta.log = c->log_dev;
+    ta.nlog = (int32_t)nlog;
+  }
+  hipStream_t s = c->stream;
+  launch_begin_call(s, c->nrep, c->kcall, c->lam);
+  for (int32_t k = 0; k < nsteps; ++k) {
+    launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->vel,
+                      c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->maxd2, c->st);
+    run_chain(c);
+    const bool timed = c->prof_every > 0 && (k + 1) % c->prof_every == 0;
+    if (timed) {
+      while (c->ev_pool.size() < c->ev_used + 2) {
+        hipEvent_t e;
+        HIPCHECK(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+      }
+      HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
+    }
+    launch_force(s, c->mixed, 1, c->tpp, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->vel,
+                 c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st);
+    if (timed) {
+      HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
+      c->ev_used += 2;
+    }
+    launch_reduce(s, c->nrep, c->reps, c->part, c->tpp, 1, ta, c->kcall, c->lam, c->rebuild,
+                  c->maxd2, c->obs, c->st);
+  }
+  if (thermo) launch_apply_lambda(s, c->ntiles, c->tiles, c->stride, c->vel, c->lam, c->nrep);
+  HIPCHECK(c, hipGetLastError());
+  md_status rc = sync_and_check(c);
+  if (rc == MD_EOVERFLOW) {
+    md_status g = grow_capacity(c);
+    c->built = false;
+    c->forces_valid = false;
+    if (g) return g;
+    return fail(c, MD_EOVERFLOW,
+                "neighbour list capacity exceeded during md_step; capacity grown, set the "
+                "state again");
+  }
+  if (rc) return rc;
+  if (log && nlog > 0)
+    HIPCHECK(c, hipMemcpy(log, c->log_dev, sizeof(md_obs) * nlog * c->nrep,
+                          hipMemcpyDeviceToHost));
+  return MD_OK;
+}
+
+md_status md_observables(md_ctx c, md_obs* out) {
+  if (!c) return MD_EINVAL;
+  if (!out) return fail(c, MD_EINVAL, "out is NULL");
+  md_status rc = sync_and_check(c);
+  if (rc) return rc;
+  HIPCHECK(c, hipMemcpy(out, c->obs, sizeof(md_obs) * c->nrep, hipMemcpyDeviceToHost));
+  return MD_OK;
+}
+
+md_status md_get_cells(md_ctx c, int32_t rep, int32_t* cell_start, int32_t* order_ids) {
+  if (!c) return MD_EINVAL;
+  if (rep < 0 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
+  if (!c->built) return fail(c, MD_ESTATE, "cells not built");
+  md_status rc = sync_and_check(c);
+  if (rc) return rc;
+  const RepDesc& d = c->reps_h[rep];
+  const int64_t ncell = (int64_t)d.nc * d.nc * d.nc;
+  if (cell_start) {
+    HIPCHECK(c, hipMemcpy(cell_start, c->cell_start + d.coff, sizeof(int32_t) * (ncell + 1),
+                          hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k <= ncell; ++k) cell_start[k] -= d.off;
+  }
+  if (order_ids) {
+    HIPCHECK(c, hipMemcpy(order_ids, c->id + d.off, sizeof(int32_t) * d.n,
+                          hipMemcpyDeviceToHost));
+    for (int32_t k = 0; k < d.n; ++k) order_ids[k] -= d.off;
+  }
+  return MD_OK;
+}
+
+md_status md_get_neighbors(md_ctx c, int32_t rep, int32_t* count, int32_t* ids, int32_t cap) {
+  if (!c) return MD_EINVAL;
+  if (rep < 0 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
+  if (!c->built) return fail(c, MD_ESTATE, "list not built");
+  if (!count || (cap > 0 && !ids) || cap < 0) return fail(c, MD_EINVAL, "bad output buffers");
+  md_status rc = sync_and_check(c);
+  if (rc) return rc;
+  const RepDesc& d = c->reps_h[rep];
+  std::vector<int32_t> cnt(d.n), idv(c->ntot);
+  HIPCHECK(c, hipMemcpy(cnt.data(), c->ncount + d.off, sizeof(int32_t) * d.n,
+                        hipMemcpyDeviceToHost));
+  HIPCHECK(c, hipMemcpy(idv.data(), c->id, sizeof(int32_t) * c->ntot, hipMemcpyDeviceToHost));
+  const int32_t rows = std::min(c->cap, cap);
+  std::vector<uint32_t> ell((size_t)std::max(rows, 1) * d.n);
+  if (rows > 0)
+    HIPCHECK(c, hipMemcpy2D(ell.data(), sizeof(uint32_t) * d.n, c->nbr + d.off,
+                            sizeof(uint32_t) * c->stride, sizeof(uint32_t) * d.n, rows,
+                            hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < d.n; ++i) {
+    const int32_t orig = idv[d.off + i] - d.off;
+    count[orig] = cnt[i];
+    const int32_t m = std::min(std::min(cnt[i], c->cap), cap);
+    for (int32_t k = 0; k < m; ++k) {
+      const uint32_t e = ell[(size_t)k * d.n + i];
+      ids[(size_t)orig * cap + k] = idv[e & kIdxMask] - d.off;
+    }
+  }
+  return MD_OK;
+}
+
+md_status md_replica_info(md_ctx c, int32_t rep, int32_t* nc, double* inv_cell, int64_t* n,
+                          int64_t* offset, int32_t* max_neighbors) {
+  if (!c) return MD_EINVAL;
+  if (rep < 0 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
+  const RepDesc& d = c->reps_h[rep];
+  if (nc) *nc = d.nc;
+  if (inv_cell) *inv_cell = d.inv_cell;
+  if (n) *n = d.n;
+  if (offset) *offset = d.off;
+  if (max_neighbors) *max_neighbors = c->cap;
+  return MD_OK;
+}
+
+md_status md_profile(md_ctx c, int32_t every) {
+  if (!c) return MD_EINVAL;
+  if (every < 0) return fail(c, MD_EINVAL, "every must be >= 0");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->prof_every = every;
+  c->ev_used = 0;
+  return MD_OK;
+}
+
+md_status md_profile_read(md_ctx c, md_prof* out) {
+  if (!c) return MD_EINVAL;
+  if (!out) return fail(c, MD_EINVAL, "out is NULL");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  out->force_launches = (int64_t)(c->ev_used / 2);
+  out->force_ms = 0.0;
+  for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.0f;
+    HIPCHECK(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+    out->force_ms += ms;
+  }
+  return MD_OK;
+}
+
+md_status md_list_stats(md_ctx c, int32_t rep, double* mean, int32_t* max) {
+  if (!c) return MD_EINVAL;
+  if (rep < -1 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
+  if (!c->built) return fail(c, MD_ESTATE, "list not built");
+  md_status rc = sync_and_check(c);
+  if (rc) return rc;
+  const int32_t off = rep < 0 ? 0 : c->reps_h[rep].off;
+  const int32_t n = rep < 0 ? c->ntot : c->reps_h[rep].n;
+  std::vector<int32_t> cnt(n);
+  HIPCHECK(c, hipMemcpy(cnt.data(), c->ncount + off, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  int64_t sum = 0;
+  int32_t m = 0;
+  for (int32_t v : cnt) {
+    sum += v;
+    m = std::max(m, v);
+  }
+  if (mean) *mean = (double)sum / (double)n;
+  if (max) *max = m;
+  return MD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// md_internal.h -- device data layout and kernel launchers of libmd (gfx950).
+//
+// Layout in HBM (particle arrays are in cell order, "sorted index" i):
+//   pos   double4[Ntot]        x, y, z, species (as a double); 32 B records
+//                              so one neighbour gather is two 16 B loads
+//   vel   double [3][stride]   SoA velocities
+//   frc   double or float [3][stride]  SoA forces
+//   xref  double [3][stride]   positions at the last list build (skin check)
+//   id    int32  [Ntot]        original (caller) index of sorted particle i
+//   img   int32  [Ntot][3]     periodic image counters, ORIGINAL id order
+//   nbr   uint32 [cap][stride] neighbour list, ELL (slot-major) so that a
+//                              wave reading slot k of 64 consecutive
+//                              particles touches one 256 B line; an entry is
+//                              (sorted j) | (image code << 26)
+// Cells: replica r owns cells [coff_r, coff_r + nc_r^3); cell_start holds
+// global particle offsets.  Particles of a replica stay in its range.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/md.h"
+
+namespace mdk {
+
+constexpr int kTile = 256;          // particles per tile == threads per block
+constexpr int kIdxBits = 26;        // neighbour index bits
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
+
+// error word bits (latched on the device, read at synchronising calls)
+enum : int32_t {
+  kErrNonFinite = 1,
+  kErrOverflow = 2,
+  kErrStray = 4,
+  kErrType = 8,
+};
+
+struct Tile {          // a run of <= kTile particles of one replica
+  int32_t rep;
+  int32_t start;
+  int32_t end;
+  int32_t pad;
+};
+
+struct RepDesc {       // per-replica geometry, device resident
+  double L;
+  double inv_cell;     // nc / L, correctly rounded on the host
+  double half_skin2;   // (skin / 2)^2
+  double dof;          // 3 n - 3
+  double volume;
+  int32_t off, n;      // particle range
+  int32_t coff, nc;    // first cell, cells per side
+  int32_t tile0, tile1;// tiles [tile0, tile1)
+};
+
+// Per species pair ab = a * 4 + b.  The pair function Eq. (3) is written as
+//   V*(r) = c12 (s/r)^12 + c6 (s/r)^6 - vc - (r - rc) fs
+//   f(r)/r = (f12 (s/r)^12 + f6 (s/r)^6) / r^2 + fs / r
+// with c6 = 0 for the soft sphere Eq. (2) and fs = 0 for a plain energy shift.
+struct PairTab {
+  double rc2[16];      // force cutoff squared
+  double thr[16];      // list threshold (rc + skin)^2
+  double sig2[16];
+  double c12[16], c6[16], f12[16], f6[16];
+  double vc[16];       // V(rc)
+  double fs[16];       // V'(rc) (shifted force) or 0
+  double rc[16];
+  double inv_mass[4];
+  double mass[4];
+};
+
+struct DevState {      // context scalars the kernels update
+  int32_t err;
+  int32_t any_rebuild;
+  int32_t pad[2];
+};
+
+// ---- launchers (each file owns its kernels) ----------------------------------
+// cells.hip
+void launch_set_state(hipStream_t s, int32_t ntot, int32_t stride, const double* x,
+                      const double* v, const int32_t* type, int32_t ntypes,
+                      double4* pos, double* vel, int32_t* id, int32_t* img, DevState* st);
+void launch_get_state(hipStream_t s, int32_t ntot, int32_t stride, const double4* pos,
+                      const double* vel, const int32_t* id, double* x, double* v);
+void launch_get_forces(hipStream_t s, int32_t ntot, int32_t stride, const void* frc,
+                       int32_t mixed, const int32_t* id, void* F);
+void launch_mark_rebuild(hipStream_t s, int32_t nrep, int32_t* rebuild, DevState* st);
+void launch_zero_counts(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
+                        const int32_t* rebuild, const DevState* st, int32_t* counts);
+void launch_bin(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
+                const int32_t* rebuild, double4* pos, const int32_t* id, int32_t* img,
+                int32_t* counts, int32_t* cell_of, int32_t* slot, DevState* st);
+void launch_scan(hipStream_t s, int32_t ncells, const int32_t* counts, int32_t* cell_start,
+                 int32_t* bsum, const DevState* st);
+size_t scan_bsum_elems(int32_t ncells);
+void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int32_t* rebuild,
+                    const int32_t* cell_of, const int32_t* slot, const int32_t* cell_start,
+                    int32_t* tmp_src);
+void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
+                        const int32_t* rebuild, const int32_t* cell_start,
+                        const int32_t* tmp_src, int32_t stride, const int32_t* id,
+                        const double4* pos, const double* vel, int32_t* id_tmp,
+                        double4* pos_tmp, double* vel_tmp);
+// nlist.hip
+void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
+                  const int32_t* rebuild, const PairTab* tab, int32_t ntypes,
+                  const int32_t* cell_start, int32_t stride, int32_t cap,
+                  const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
+                  double4* pos, double* vel, int32_t* id, double* xref,
+                  uint32_t* nbr, int32_t* ncount, DevState* st);
+// force.hip
+// mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
+// half kick v += dt/2 F/m before KE.
+void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t ntiles,
+                  const Tile* tiles, const RepDesc* reps, const PairTab* tab,
+                  const double4* pos, double* vel, void* frc, const uint32_t* nbr,
+                  const int32_t* ncount, int32_t stride, int32_t cap, double dt,
+                  double* part, DevState* st);
+// integrate.hip
+void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t ntiles,
+                       const Tile* tiles, const RepDesc* reps, const PairTab* tab,
+                       double4* pos, double* vel, const void* frc, const double* xref,
+                       int32_t stride, double dt, const double* lam, int32_t* rebuild,
+                       unsigned long long* maxd2, DevState* st);
+struct ThermoArgs {
+  const double* T0;    // [nrep]
+  const double* T1;    // [nrep]
+  int64_t ramp;
+  int32_t thermo;      // 0 = NVE
+  int32_t log_every;   // 0 = no log
+  md_obs* log;         // [nlog][nrep]
+  int32_t nlog;
+  int32_t pad;
+};
+// step = 0: observables of the current state only; step = 1: end of a step
+// part holds one (pe, w, ke) triple per force block; replica r owns blocks
+// [tile0 * tpp, tile1 * tpp).
+void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
+                   int32_t tpp, int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
+                   int32_t* rebuild, unsigned long long* maxd2, md_obs* obs, DevState* st);
+void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild,
+                        unsigned long long* maxd2, md_obs* obs, DevState* st);
+void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam);
+void launch_apply_lambda(hipStream_t s, int32_t ntiles, const Tile* tiles, int32_t stride,
+                         double* vel, double* lam, int32_t nrep);
+
+}  // namespace mdk

@@ -1,0 +1,273 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: cell arrays and neighbour lists bit-exact (canonical sorted sets);
+FP64 forces within e = max_i |dF_i| / max(|F_i|, F_rms) <= 1e-12 and
+energies/virial within 1e-12 relative; mixed precision e <= 1e-5 and
+energy/virial <= 1e-6 relative.  Every comparison is on the same state
+(downloaded from the GPU when the GPU has been stepping): trajectories of two
+chaotic integrations are never compared beyond a few steps.
+"""
+import numpy as np
+import pytest
+
+import initconf
+import oracle
+from gpu_common import (canonical, drift_slope, floored_err, lib_params, oracle_cells_lists,
+                        oracle_params)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def make_system(torch_cuda, n, seed, precision=0, T=2.0, **kw):
+    from paper_1105_5613_amd import System
+    s = initconf.fcc_system(n, seed=seed, temperature=T)
+    sysm = System(lib_params(precision=precision, **kw), [n], [s["L"]])
+    sysm.set_state(s["x"], s["v"], s["type"])
+    return sysm, s
+
+
+def compare_cells_lists(sysm, p, x, types, L, rep=0, tag=""):
+    xw, cs, order, count, ids, nc = oracle_cells_lists(p, x, types, L)
+    gcs, gorder = sysm.get_cells(rep)
+    assert sysm.replica_info(rep)["nc"] == nc
+    assert np.array_equal(gcs, cs), f"{tag}: cell_start differs"
+    assert np.array_equal(gorder, order), f"{tag}: cell order differs"
+    gcount, gids = sysm.get_neighbors(rep, cap=ids.shape[1])
+    assert np.array_equal(gcount, count), f"{tag}: neighbour counts differ"
+    assert np.array_equal(canonical(gcount, gids), canonical(count, ids)), f"{tag}: lists differ"
+    return xw, count, ids
+
+
+@pytest.mark.parametrize("n,seed", [(4000, 1), (32000, 7), (500, 3)])
+def test_cells_lists_forces_fp64(torch_cuda, n, seed):
+    say(f"case cells/lists/forces fp64 n={n} seed={seed}")
+    sysm, s = make_system(torch_cuda, n, seed)
+    p = oracle_params()
+    sysm.build_cells()
+    xw, count, ids = compare_cells_lists(sysm, p, s["x"], s["type"], s["L"], tag=f"n={n}")
+    sysm.forces()
+    F = sysm.get_forces().cpu().numpy()
+    Fo, peo, wo = oracle.forces_list(p, xw, s["type"], s["L"], count, ids)
+    e = floored_err(F, Fo)
+    say(f"  force error {e:.3e}")
+    assert e <= 1e-12
+    ob = sysm.observables()[0]
+    assert ob["pe"] == pytest.approx(peo, rel=1e-12)
+    assert ob["virial"] == pytest.approx(wo, rel=1e-12)
+    ke = 0.5 * np.sum(s["v"] ** 2)
+    assert ob["ke"] == pytest.approx(ke, rel=1e-12)
+    V = s["L"] ** 3
+    assert ob["P"] == pytest.approx((2 * ke + wo) / (3 * V), rel=1e-12)
+    assert ob["n_rebuild"] == 1
+
+
+def test_forces_mixed(torch_cuda):
+    say("case forces mixed n=32000")
+    sysm, s = make_system(torch_cuda, 32000, 7, precision=1)
+    p = oracle_params()
+    sysm.forces()
+    F = sysm.get_forces().cpu().numpy()
+    assert F.dtype == np.float32
+    Fo, pe_i, w_i = oracle.forces_cells(p, s["x"], s["type"], s["L"])
+    e = floored_err(F, Fo)
+    say(f"  mixed force error {e:.3e}")
+    assert e <= 1e-5
+    ob = sysm.observables()[0]
+    assert ob["pe"] == pytest.approx(pe_i.sum(), rel=1e-6)
+    assert ob["virial"] == pytest.approx(w_i.sum(), rel=1e-6)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_states_after_steps(torch_cuda, precision):
+    """Cells, lists and forces re-checked on states reached by stepping."""
+    say(f"case stepped states precision={precision}")
+    sysm, s = make_system(torch_cuda, 4000, 1, precision=precision)
+    p = oracle_params()
+    done = 0
+    for target in (10, 50, 100):
+        sysm.step(target - done)
+        done = target
+        x, v, img = sysm.get_state()
+        x = x.cpu().numpy()
+        sysm.build_cells()
+        xw, count, ids = compare_cells_lists(sysm, p, x, s["type"], s["L"], tag=f"step {target}")
+        sysm.forces()
+        F = sysm.get_forces().cpu().numpy()
+        Fo, peo, wo = oracle.forces_list(p, xw, s["type"], s["L"], count, ids)
+        e = floored_err(F, Fo)
+        say(f"  step {target}: force error {e:.3e}")
+        assert e <= (1e-12 if precision == 0 else 1e-5)
+        ob = sysm.observables()[0]
+        assert ob["pe"] == pytest.approx(peo, rel=1e-12 if precision == 0 else 1e-6)
+
+
+def test_short_trajectory_matches_oracle(torch_cuda):
+    """FP64: 20 steps from the same start agree far below the chaos horizon."""
+    say("case short trajectory fp64")
+    sysm, s = make_system(torch_cuda, 4000, 1)
+    sim = oracle.Sim(oracle_params(), 4000, s["L"], 0.005)
+    sim.set_state(s["x"], s["v"], s["type"])
+    log = sysm.step(20, log_every=1)
+    ref = sim.step(20)
+    x, v, img = sysm.get_state()
+    xo, vo, imgo = sim.get_state()
+    xu = x.cpu().numpy() + img.cpu().numpy() * s["L"]
+    xou = xo + imgo * s["L"]
+    assert np.max(np.abs(xu - xou)) < 1e-9
+    assert np.max(np.abs(v.cpu().numpy() - vo)) < 1e-8
+    assert np.allclose(log["E"][:, 0], ref["E"], rtol=1e-10)
+    assert np.array_equal(log["step"][:, 0], np.arange(1, 21))
+
+
+def test_nve_drift_fp64_and_mixed(torch_cuda):
+    """4,000 particles, dt = 0.005: steady-state drift below 1e-4 per particle."""
+    for precision in (0, 1):
+        say(f"case drift precision={precision}")
+        sysm, s = make_system(torch_cuda, 4000, 1, precision=precision)
+        log = sysm.step(1100, log_every=1)
+        D = drift_slope(log["E"][:, 0], 4000)
+        say(f"  drift D = {D:.3e}, rebuilds = {log['n_rebuild'][-1, 0]}")
+        assert D <= 1e-4
+        assert log["n_rebuild"][-1, 0] > 10
+
+
+def test_thermostat_and_ramp(torch_cuda):
+    say("case thermostat")
+    sysm, s = make_system(torch_cuda, 4000, 5, T=2.0)
+    log = sysm.step(30, T0=0.8, log_every=1)
+    assert np.allclose(log["T"][:, 0], 0.8, rtol=1e-13)
+    _, v, _ = sysm.get_state()
+    v = v.cpu().numpy()
+    assert np.sum(v * v) / (3 * 4000 - 3) == pytest.approx(0.8, rel=1e-13)
+    log = sysm.step(40, T0=0.8, T1=0.4, ramp=20, log_every=1)
+    expect = 0.8 + (0.4 - 0.8) * np.minimum(np.arange(1, 41) / 20, 1.0)
+    assert np.allclose(log["T"][:, 0], expect, rtol=1e-13)
+    assert np.allclose(log["T_target"][:, 0], expect, rtol=1e-15)
+
+
+def test_thermostat_matches_oracle(torch_cuda):
+    say("case thermostat vs oracle")
+    sysm, s = make_system(torch_cuda, 4000, 5, T=2.0)
+    sim = oracle.Sim(oracle_params(), 4000, s["L"], 0.005)
+    sim.set_state(s["x"], s["v"], s["type"])
+    log = sysm.step(10, T0=1.0, T1=0.5, ramp=10, log_every=1)
+    ref = sim.step(10, T0=1.0, T1=0.5, ramp=10)
+    assert np.allclose(log["pe"][:, 0], ref["pe"], rtol=1e-10)
+    assert np.allclose(log["T"][:, 0], ref["T"], rtol=1e-12)
+
+
+def test_batched_replicas(torch_cuda):
+    """Uneven replicas in one context: each matches the oracle on its own box."""
+    from paper_1105_5613_amd import System
+    say("case batched replicas")
+    sizes = [1000, 3001, 500, 8788, 2048]
+    temps = [0.4, 1.0, 2.0, 1.5, 0.7]
+    systems = initconf.batched_systems(sizes, temps, seed=9)
+    x, v, t, n, L = initconf.concat_replicas(systems)
+    for precision in (0, 1):
+        sysm = System(lib_params(precision=precision), n, L)
+        sysm.set_state(x, v, t)
+        sysm.build_cells()
+        sysm.forces()
+        F = sysm.get_forces().cpu().numpy()
+        obs = sysm.observables()
+        p = oracle_params()
+        off = 0
+        for r, sy in enumerate(systems):
+            xw, count, ids = compare_cells_lists(sysm, p, sy["x"], sy["type"], sy["L"], rep=r,
+                                                 tag=f"replica {r}")
+            Fo, peo, wo = oracle.forces_list(p, xw, sy["type"], sy["L"], count, ids)
+            e = floored_err(F[off:off + sy["n"]], Fo)
+            assert e <= (1e-12 if precision == 0 else 1e-5), (r, e)
+            assert obs[r]["pe"] == pytest.approx(peo, rel=1e-12 if precision == 0 else 1e-6)
+            off += sy["n"]
+        # stepping with per-replica thermostat targets
+        log = sysm.step(20, T0=temps, log_every=5)
+        assert np.allclose(log["T"][-1], temps, rtol=1e-12)
+
+
+def test_error_paths(torch_cuda):
+    from paper_1105_5613_amd import MDError, System
+    say("case error paths")
+    s = initconf.fcc_system(500, seed=3)
+    # box smaller than 2 (rc + skin)
+    with pytest.raises(MDError) as ex:
+        System(lib_params(), [500], [5.0])
+    assert ex.value.code == -3
+    # bad species
+    sysm = System(lib_params(), [500], [s["L"]])
+    bad = s["type"].copy()
+    bad[7] = 5
+    with pytest.raises(MDError) as ex:
+        sysm.set_state(s["x"], s["v"], bad)
+    assert ex.value.code == -1
+    # non-finite input
+    xb = s["x"].copy()
+    xb[3, 1] = np.nan
+    with pytest.raises(MDError) as ex:
+        sysm.set_state(xb, s["v"], s["type"])
+    assert ex.value.code == -5
+    # out of order
+    fresh = System(lib_params(), [500], [s["L"]])
+    with pytest.raises(MDError) as ex:
+        fresh.forces()
+    assert ex.value.code == -7
+    # a tiny neighbour capacity grows on the first build
+    small = System(lib_params(max_neighbors=8), [500], [s["L"]])
+    small.set_state(s["x"], s["v"], s["type"])
+    small.build_cells()
+    assert small.replica_info()["max_neighbors"] > 8
+    p = oracle_params()
+    compare_cells_lists(small, p, s["x"], s["type"], s["L"], tag="grown capacity")
+
+
+def test_large_box_sampled(torch_cuda):
+    """1,048,576 particles: full lists bit-exact, sampled forces vs the oracle."""
+    say("case 1M particles")
+    n = 1048576
+    for precision in (0, 1):
+        sysm, s = make_system(torch_cuda, n, 2, precision=precision)
+        p = oracle_params()
+        sysm.step(20)
+        x, v, img = sysm.get_state()
+        x = x.cpu().numpy()
+        sysm.build_cells()
+        xw, count, ids = compare_cells_lists(sysm, p, x, s["type"], s["L"], tag="1M")
+        sysm.forces()
+        F = sysm.get_forces().cpu().numpy()
+        sel = np.random.default_rng(0).choice(n, 4096, replace=False)
+        Fo, _, _ = oracle.forces_cells(p, x, s["type"], s["L"], sel=sel)
+        Fall = np.linalg.norm(F, axis=1)
+        frms = float(np.sqrt(np.mean(Fall ** 2)))
+        d = np.linalg.norm(F[sel].astype(np.float64) - Fo, axis=1)
+        e = float(np.max(d / np.maximum(np.linalg.norm(Fo, axis=1), frms)))
+        say(f"  precision {precision}: sampled force error {e:.3e}")
+        assert e <= (1e-12 if precision == 0 else 1e-5)
+        # the total force vanishes to round-off (full list: both sides of a pair)
+        assert np.max(np.abs(F.astype(np.float64).sum(axis=0))) <= \
+            (1e-9 if precision == 0 else 1e-2) * np.sum(Fall)
+
+
+def test_deterministic(torch_cuda):
+    """Two runs from the same state give identical bits (fixed reduction order)."""
+    say("case determinism")
+    outs = []
+    for _ in range(2):
+        sysm, s = make_system(torch_cuda, 32000, 7)
+        log = sysm.step(30, log_every=1)
+        x, v, img = sysm.get_state()
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), log["E"]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
