@@ -80,7 +80,8 @@ typedef struct {
   int32_t max_neighbors; /* neighbour capacity per particle; 0 = from density */
   int32_t graph_steps;   /* steps per captured hipGraph in md_step; 0 = direct */
   int32_t tpp;           /* lanes per particle in the force kernel (1,2,4,8); 0 = auto */
-  int32_t reserved;
+  int32_t unroll;        /* list slots gathered per pipelined chunk in the force
+                            kernel (1,2,4,8); 0 = auto */
 } md_params;
 
 /* Per-replica observables after the last completed step. */

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
                                                int32_t* __restrict__ counts,
                                                int32_t* __restrict__ cell_of,
                                                int32_t* __restrict__ slot, DevState* st) {
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   if (!rebuild[t.rep]) return;
   const int32_t i = t.start + threadIdx.x;
   if (i >= t.end) return;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kTile) void k_scatter(const Tile* __restrict__ tile
                                                    const int32_t* __restrict__ slot,
                                                    const int32_t* __restrict__ cell_start,
                                                    int32_t* __restrict__ tmp_src) {
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   if (!rebuild[t.rep]) return;
   const int32_t i = t.start + threadIdx.x;
   if (i >= t.end) return;

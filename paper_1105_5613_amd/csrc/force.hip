@@ -12,7 +12,10 @@
 //
 // One thread per particle (tpp = 1) walks its ELL row; threads per particle
 // tpp in {2, 4, 8} split the row into interleaved slots and combine their
-// partial sums with cross-lane shuffles.
+// partial sums with cross-lane shuffles.  The walk is software-pipelined: the
+// list entries of the next chunk of U slots are loaded while the U gathered
+// neighbour positions of the current chunk are processed, so each lane keeps
+// U gathers and U index loads in flight instead of one dependent pair.
 #include "md_internal.h"
 
 namespace mdk {
@@ -83,7 +86,7 @@ __device__ inline void block_sum3(double& a, double& b, double& c) {
   }
 }
 
-template <bool MIXED, int MODE, int TPP>
+template <bool MIXED, int MODE, int TPP, int U>
 __global__ __launch_bounds__(kTile) void k_force(
     const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
     const PairTab* __restrict__ tab, const double4* __restrict__ pos, double* __restrict__ vel,
@@ -97,9 +100,10 @@ __global__ __launch_bounds__(kTile) void k_force(
   __syncthreads();
 
   // with TPP lanes per particle a block covers kTile / TPP particles; a tile
-  // of kTile particles takes TPP consecutive blocks
-  const int32_t tile_id = blockIdx.x / TPP;
-  const int32_t sub = blockIdx.x % TPP;
+  // of kTile particles takes TPP consecutive (logical) blocks
+  const int32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int32_t tile_id = lb / TPP;
+  const int32_t sub = lb % TPP;
   const Tile t = tiles[tile_id];
   const double L = reps[t.rep].L;
   const int32_t lane_p = threadIdx.x % TPP;
@@ -109,44 +113,65 @@ __global__ __launch_bounds__(kTile) void k_force(
   double pe = 0.0, w = 0.0, ke = 0.0;
   T fx = 0, fy = 0, fz = 0;
   T pe_i = 0, w_i = 0;
-  double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
   int32_t ti = 0;
   if (active) {
-    p = pos[i];
+    const double4 p = pos[i];
     ti = (int32_t)p.w;
     int32_t n = ncount[i];
     n = n < cap ? n : cap;
     const uint32_t* row = nbr + i;
-    for (int32_t k = lane_p; k < n; k += TPP) {
-      const uint32_t e = row[(size_t)k * stride];
-      const double4 q = pos[e & kIdxMask];
-      double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-      if (e >> kIdxBits) {
-        // x_i - (x_j + s L)
-        dx -= (double)decode_shift(e, 26) * L;
-        dy -= (double)decode_shift(e, 28) * L;
-        dz -= (double)decode_shift(e, 30) * L;
+    // entries are fetched one chunk of U ahead; slots past n point at the
+    // particle itself and are masked out
+    const uint32_t self = (uint32_t)i;
+    uint32_t e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t k = lane_p + u * TPP;
+      e[u] = k < n ? row[(size_t)k * stride] : self;
+    }
+    for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
+      double4 q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u] = pos[e[u] & kIdxMask];
+      uint32_t en[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t k = k0 + (U + u) * TPP;
+        en[u] = k < n ? row[(size_t)k * stride] : self;
       }
-      const int32_t ab = ti * 4 + (int32_t)q.w;
-      const T ddx = (T)dx, ddy = (T)dy, ddz = (T)dz;
-      const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-      if (r2 < P.rc2[ab]) {
-        T rinv;
-        if constexpr (MIXED)
-          rinv = __builtin_amdgcn_rsqf(r2);
-        else
-          rinv = rsqrt_nr(r2);
-        const T r2inv = rinv * rinv;
-        const T sr2 = P.sig2[ab] * r2inv;
-        const T sr6 = sr2 * sr2 * sr2;
-        const T sr12 = sr6 * sr6;
-        const T fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
-        fx += fr * ddx;
-        fy += fr * ddy;
-        fz += fr * ddz;
-        pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] - (r2 * rinv - P.rc[ab]) * P.fs[ab];
-        w_i += fr * r2;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        double dx = p.x - q[u].x, dy = p.y - q[u].y, dz = p.z - q[u].z;
+        if (e[u] >> kIdxBits) {
+          // x_i - (x_j + s L)
+          dx -= (double)decode_shift(e[u], 26) * L;
+          dy -= (double)decode_shift(e[u], 28) * L;
+          dz -= (double)decode_shift(e[u], 30) * L;
+        }
+        const int32_t ab = ti * 4 + (int32_t)q[u].w;
+        const T ddx = (T)dx, ddy = (T)dy, ddz = (T)dz;
+        const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+        if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
+          T rinv;
+          if constexpr (MIXED)
+            rinv = __builtin_amdgcn_rsqf(r2);
+          else
+            rinv = rsqrt_nr(r2);
+          const T r2inv = rinv * rinv;
+          const T sr2 = P.sig2[ab] * r2inv;
+          const T sr6 = sr2 * sr2 * sr2;
+          const T sr12 = sr6 * sr6;
+          const T fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
+          fx += fr * ddx;
+          fy += fr * ddy;
+          fz += fr * ddz;
+          pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
+                  (r2 * rinv - P.rc[ab]) * P.fs[ab];
+          w_i += fr * r2;
+        }
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u) e[u] = en[u];
     }
   }
   if constexpr (TPP > 1) {
@@ -182,7 +207,7 @@ __global__ __launch_bounds__(kTile) void k_force(
   }
   block_sum3(pe, w, ke);
   if (threadIdx.x == 0) {
-    double* o = part + 4 * (size_t)blockIdx.x;
+    double* o = part + 4 * (size_t)lb;
     o[0] = pe;
     o[1] = w;
     o[2] = ke;
@@ -190,52 +215,48 @@ __global__ __launch_bounds__(kTile) void k_force(
 }
 
 template <bool MIXED, int MODE>
-void launch_t(hipStream_t s, int32_t tpp, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
-              const PairTab* tab, const double4* pos, double* vel, void* frc,
-              const uint32_t* nbr, const int32_t* ncount, int32_t stride, int32_t cap, double dt,
-              double* part, DevState* st) {
-  switch (tpp) {
-    case 2:
-      k_force<MIXED, MODE, 2><<<ntiles * 2, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, nbr,
-                                                           ncount, stride, cap, dt, part, st);
-      break;
-    case 4:
-      k_force<MIXED, MODE, 4><<<ntiles * 4, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, nbr,
-                                                           ncount, stride, cap, dt, part, st);
-      break;
-    case 8:
-      k_force<MIXED, MODE, 8><<<ntiles * 8, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, nbr,
-                                                           ncount, stride, cap, dt, part, st);
-      break;
-    default:
-      k_force<MIXED, MODE, 1><<<ntiles, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, nbr,
-                                                       ncount, stride, cap, dt, part, st);
+void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const Tile* tiles,
+              const RepDesc* reps, const PairTab* tab, const double4* pos, double* vel,
+              void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride, int32_t cap,
+              double dt, double* part, DevState* st) {
+#define KF(TPP, U)                                                                            \
+  k_force<MIXED, MODE, TPP, U><<<ntiles * TPP, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, \
+                                                              nbr, ncount, stride, cap, dt,    \
+                                                              part, st)
+  const int key = tpp * 16 + unroll;
+  switch (key) {
+    case 1 * 16 + 1: KF(1, 1); break;
+    case 1 * 16 + 2: KF(1, 2); break;
+    case 1 * 16 + 8: KF(1, 8); break;
+    case 2 * 16 + 1: KF(2, 1); break;
+    case 2 * 16 + 2: KF(2, 2); break;
+    case 2 * 16 + 4: KF(2, 4); break;
+    case 4 * 16 + 1: KF(4, 1); break;
+    case 4 * 16 + 2: KF(4, 2); break;
+    case 8 * 16 + 1: KF(8, 1); break;
+    default: KF(1, 4); break;
   }
+#undef KF
 }
 
 }  // namespace
 
-// Partials: one FP64 triple (pe, w, ke) per launched block; with tpp lanes
-// per particle, tile t owns blocks [t*tpp, (t+1)*tpp).
-void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t ntiles,
-                  const Tile* tiles, const RepDesc* reps, const PairTab* tab, const double4* pos,
-                  double* vel, void* frc, const uint32_t* nbr, const int32_t* ncount,
-                  int32_t stride, int32_t cap, double dt, double* part, DevState* st) {
+// Partials: one FP64 triple (pe, w, ke) per logical block; with tpp lanes
+// per particle, tile t owns logical blocks [t*tpp, (t+1)*tpp).
+void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
+                  int32_t ntiles, const Tile* tiles, const RepDesc* reps, const PairTab* tab,
+                  const double4* pos, double* vel, void* frc, const uint32_t* nbr,
+                  const int32_t* ncount, int32_t stride, int32_t cap, double dt, double* part,
+                  DevState* st) {
+#define LT(M, MO)                                                                              \
+  launch_t<M, MO>(s, tpp, unroll, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride, \
+                  cap, dt, part, st)
   if (mixed) {
-    if (mode)
-      launch_t<true, 1>(s, tpp, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride, cap,
-                        dt, part, st);
-    else
-      launch_t<true, 0>(s, tpp, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride, cap,
-                        dt, part, st);
+    if (mode) LT(true, 1); else LT(true, 0);
   } else {
-    if (mode)
-      launch_t<false, 1>(s, tpp, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride,
-                         cap, dt, part, st);
-    else
-      launch_t<false, 0>(s, tpp, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride,
-                         cap, dt, part, st);
+    if (mode) LT(false, 1); else LT(false, 0);
   }
+#undef LT
 }
 
 }  // namespace mdk

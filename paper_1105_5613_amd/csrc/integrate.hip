@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kTile) void k_kick_drift(
   __shared__ double s_red[kTile / 64];
   if (threadIdx.x < 4) s_im[threadIdx.x] = tab->inv_mass[threadIdx.x];
   __syncthreads();
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   const int32_t i = t.start + threadIdx.x;
   double d2 = 0.0;
   if (i < t.end) {
@@ -174,7 +174,7 @@ __global__ void k_begin_call(int32_t nrep, int64_t* kcall, double* lam) {
 __global__ __launch_bounds__(kTile) void k_apply_lambda(const Tile* __restrict__ tiles,
                                                         int32_t stride, double* __restrict__ vel,
                                                         const double* __restrict__ lam) {
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   const int32_t i = t.start + threadIdx.x;
   if (i >= t.end) return;
   const double l = lam[t.rep];

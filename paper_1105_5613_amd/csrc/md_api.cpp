@@ -15,7 +15,7 @@ using namespace mdk;
 
 struct md_ctx_s {
   md_params p{};
-  int32_t nrep = 0, ntot = 0, stride = 0, ncells = 0, ntiles = 0, cap = 0, tpp = 1;
+  int32_t nrep = 0, ntot = 0, stride = 0, ncells = 0, ntiles = 0, cap = 0, tpp = 1, unroll = 4;
   int32_t mixed = 0;
   hipStream_t stream = nullptr;
   std::vector<RepDesc> reps_h;
@@ -138,6 +138,8 @@ md_status validate(const md_params* p, std::string* why) {
   if (p->tpp != 0 && p->tpp != 1 && p->tpp != 2 && p->tpp != 4 && p->tpp != 8)
     return *why = "tpp must be 0, 1, 2, 4 or 8", MD_EINVAL;
   if (p->graph_steps < 0) return *why = "graph_steps must be >= 0", MD_EINVAL;
+  if (p->unroll != 0 && p->unroll != 1 && p->unroll != 2 && p->unroll != 4 && p->unroll != 8)
+    return *why = "unroll must be 0, 1, 2, 4 or 8", MD_EINVAL;
   return MD_OK;
 }
 
@@ -213,7 +215,7 @@ ThermoArgs no_thermo() {
 }
 
 void launch_forces0(md_ctx c) {
-  launch_force(c->stream, c->mixed, 0, c->tpp, c->ntiles, c->tiles, c->reps, c->tab, c->pos,
+  launch_force(c->stream, c->mixed, 0, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps, c->tab, c->pos,
                c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st);
   launch_reduce(c->stream, c->nrep, c->reps, c->part, c->tpp, 0, no_thermo(), c->kcall, c->lam,
                 c->rebuild, c->maxd2, c->obs, c->st);
@@ -249,7 +251,8 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
   c->ntot = (int32_t)ntot;
   c->stride = (int32_t)(((ntot + 63) / 64) * 64);
   c->mixed = p->precision == MD_MIXED;
-  c->tpp = p->tpp == 0 ? 1 : p->tpp;
+  c->tpp = p->tpp == 0 ? 2 : p->tpp;
+  c->unroll = p->unroll == 0 ? 4 : p->unroll;
   c->stream = (hipStream_t)hip_stream;
 
   // replica geometry: cells of side >= max rc + skin (nc < 3 -> one cell)
@@ -535,7 +538,7 @@ md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
       }
       HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
     }
-    launch_force(s, c->mixed, 1, c->tpp, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->vel,
+    launch_force(s, c->mixed, 1, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->vel,
                  c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st);
     if (timed) {
       HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));

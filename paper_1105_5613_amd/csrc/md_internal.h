@@ -70,6 +70,17 @@ struct PairTab {
   double mass[4];
 };
 
+// The hardware deals consecutive workgroups of a launch round-robin to the 8
+// XCDs, each with its own L2.  Renumber blocks so that XCD x runs one
+// contiguous run of logical blocks: neighbouring tiles (which gather the same
+// neighbour positions) then share an L2.  Bijective for any grid size.
+constexpr int kXcd = 8;
+__device__ inline int32_t xcd_block(int32_t b, int32_t nb) {
+  const int32_t q = nb / kXcd, r = nb % kXcd;
+  const int32_t x = b % kXcd, k = b / kXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
 struct DevState {      // context scalars the kernels update
   int32_t err;
   int32_t any_rebuild;
@@ -112,8 +123,9 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
 // force.hip
 // mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
 // half kick v += dt/2 F/m before KE.
-void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t ntiles,
-                  const Tile* tiles, const RepDesc* reps, const PairTab* tab,
+// unroll: list slots gathered per pipelined chunk (1, 2, 4 or 8).
+void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
+                  int32_t ntiles, const Tile* tiles, const RepDesc* reps, const PairTab* tab,
                   const double4* pos, double* vel, void* frc, const uint32_t* nbr,
                   const int32_t* ncount, int32_t stride, int32_t cap, double dt,
                   double* part, DevState* st);

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
   __shared__ double s_thr[16];
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   if (!rebuild[t.rep]) return;
   const int32_t i = t.start + threadIdx.x;
   if (i >= t.end) return;

@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("eps", C.c_double * 16), ("sig", C.c_double * 16),
                 ("rc", C.c_double * 16), ("mass", C.c_double * 4), ("skin", C.c_double),
                 ("dt", C.c_double), ("max_neighbors", C.c_int32), ("graph_steps", C.c_int32),
-                ("tpp", C.c_int32), ("reserved", C.c_int32)]
+                ("tpp", C.c_int32), ("unroll", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -97,7 +97,7 @@ def lib():
 
 def make_params(eps, sig, rc, mass, *, skin=0.3, dt=0.005, precision=MD_FP64,
                 potential=MD_POT_LJ, trunc=MD_TRUNC_SHIFTED_FORCE, max_neighbors=0,
-                graph_steps=0, tpp=0) -> Params:
+                graph_steps=0, tpp=0, unroll=0) -> Params:
     p = Params()
     nt = len(eps)
     p.ntypes = nt
@@ -115,6 +115,7 @@ def make_params(eps, sig, rc, mass, *, skin=0.3, dt=0.005, precision=MD_FP64,
     p.max_neighbors = int(max_neighbors)
     p.graph_steps = int(graph_steps)
     p.tpp = int(tpp)
+    p.unroll = int(unroll)
     return p
 
 
