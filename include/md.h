@@ -61,6 +61,13 @@ enum {
 enum { MD_POT_LJ = 0, MD_POT_SOFT = 1 };
 enum { MD_TRUNC_SHIFTED_FORCE = 0, MD_TRUNC_SHIFT = 1 };
 enum { MD_FP64 = 0, MD_MIXED = 1 };
+/* Kernel path.  GATHER: one thread group per particle gathers neighbour
+ * positions from global memory; list entries are 32-bit indices with a
+ * periodic-image code; works for any box.  STAGED: one block per row of
+ * cells stages the neighbourhood (with periodic shifts applied) in LDS and
+ * list entries are 16-bit LDS slots; needs >= 3 cells per box side.  AUTO
+ * is GATHER, the faster path on MI355X at the measured sizes. */
+enum { MD_PATH_AUTO = 0, MD_PATH_GATHER = 1, MD_PATH_STAGED = 2 };
 #define MD_MAXT 4
 
 /* Physical and numerical parameters, shared by all replicas of a context. */
@@ -82,6 +89,11 @@ typedef struct {
   int32_t tpp;           /* lanes per particle in the force kernel (1,2,4,8); 0 = auto */
   int32_t unroll;        /* list slots gathered per pipelined chunk in the force
                             kernel (1,2,4,8); 0 = auto */
+  int32_t path;          /* MD_PATH_AUTO, MD_PATH_GATHER or MD_PATH_STAGED */
+  int32_t tile_threads;  /* staged path: threads per row-tile block (128, 256); 0 = auto */
+  int32_t tile_cells;    /* staged path: cells per row tile (1..64); 0 = auto */
+  int32_t stage_slots;   /* staged path: LDS slots per tile (>= 64); slots beyond are
+                            read from global memory; 0 = auto */
 } md_params;
 
 /* Per-replica observables after the last completed step. */

@@ -1,0 +1,229 @@
+// force_staged.hip -- the pair-force hot spot on the staged path: one block
+// per row tile stages the tile's neighbourhood (positions with their periodic
+// shift applied, FP64) into LDS one z-slab of rows at a time, and each home
+// particle walks the part of its 16-bit slot list that belongs to the slab.  Same pair arithmetic as force.hip: shifted-force
+// Eq. (3) on Eq. (1)/(2), FP64 with an FP32-seeded two-step Newton-Raphson
+// 1/r, or FP32 pair math from the FP64 displacement (mixed); per-particle
+// energy/virial halves widened to FP64 and reduced per tile.
+#include "stage.h"
+
+namespace mdk {
+namespace {
+
+__device__ inline double rsqrt_nr(double r2) {
+  double y = (double)__builtin_amdgcn_rsqf((float)r2);
+  const double h = 0.5 * r2;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
+
+template <typename T>
+struct PairLds {
+  T rc2[16], sig2[16], c12[16], c6[16], f12[16], f6[16], vc[16], fs[16], rc[16];
+};
+
+template <int BT>
+__device__ inline void block_sum3(double& a, double& b, double& c) {
+  __shared__ double red[3][BT / 64];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    a += __shfl_xor(a, d, 64);
+    b += __shfl_xor(b, d, 64);
+    c += __shfl_xor(c, d, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+    red[2][w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = red[0][0];
+    b = red[1][0];
+    c = red[2][0];
+    for (int k = 1; k < BT / 64; ++k) {
+      a += red[0][k];
+      b += red[1][k];
+      c += red[2][k];
+    }
+  }
+}
+
+template <bool MIXED, int MODE, int BT, int U>
+__global__ __launch_bounds__(BT) void k_force_staged(
+    const RowTile* __restrict__ rtiles, const RepDesc* __restrict__ reps,
+    const PairTab* __restrict__ tab, const int32_t* __restrict__ cell_start,
+    const double4* __restrict__ pos, double* __restrict__ vel, void* __restrict__ frc_,
+    const uint16_t* __restrict__ nbr, const int32_t* __restrict__ ncount,
+    const uint32_t* __restrict__ nsplit, int32_t stride, int32_t cap, int32_t lcap, double dt,
+    double* __restrict__ part, DevState* st) {
+  using T = typename std::conditional<MIXED, float, double>::type;
+  __shared__ StageLayout S;
+  __shared__ PairLds<T> P;
+  __shared__ double s_mass[4];
+  extern __shared__ double dyn[];
+  const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
+  const RowTile Tl = rtiles[tb];
+  const RepDesc R = reps[Tl.rep];
+  if (threadIdx.x < 16) {
+    const int k = threadIdx.x;
+    P.rc2[k] = (T)tab->rc2[k];
+    P.sig2[k] = (T)tab->sig2[k];
+    P.c12[k] = (T)tab->c12[k];
+    P.c6[k] = (T)tab->c6[k];
+    P.f12[k] = (T)tab->f12[k];
+    P.f6[k] = (T)tab->f6[k];
+    P.vc[k] = (T)tab->vc[k];
+    P.fs[k] = (T)tab->fs[k];
+    P.rc[k] = (T)tab->rc[k];
+  }
+  if (threadIdx.x < 4) s_mass[threadIdx.x] = tab->mass[threadIdx.x];
+  build_layout(S, Tl, R, cell_start);
+  double* xs = dyn;
+  double* ys = xs + lcap;
+  double* zs = ys + lcap;
+
+  double pe = 0.0, w = 0.0, ke = 0.0;
+  const int32_t nh = S.home1 - S.home0;
+  // home particles in groups of BT (one per thread); the passes restage per group
+  for (int32_t g0 = 0; g0 < nh; g0 += BT) {
+    const int32_t li = g0 + (int32_t)threadIdx.x;
+    const bool mine = li < nh;
+    const int32_t i = S.home0 + (mine ? li : 0);
+    const double4 p = pos[i];
+    const int32_t ti = (int32_t)p.w;
+    const int32_t n = mine ? (ncount[i] < cap ? ncount[i] : cap) : 0;
+    const uint32_t sp = mine ? nsplit[i] : 0u;
+    const int32_t n0 = (int32_t)(sp & 0xffffu), n1 = (int32_t)(sp >> 16);
+    const uint16_t* row = nbr + i;
+    T fx = 0, fy = 0, fz = 0, pe_i = 0, w_i = 0;
+    for (int pass = 0; pass < 3; ++pass) {
+      const int32_t base = pass_base(S, pass);
+      stage<false>(S, pass, pos, lcap, xs, ys, zs, nullptr);
+      int32_t k0 = pass == 0 ? 0 : (pass == 1 ? n0 : n0 + n1);
+      int32_t k1 = pass == 0 ? n0 : (pass == 1 ? n0 + n1 : n);
+      k0 = k0 < n ? k0 : n;
+      k1 = k1 < n ? k1 : n;
+      // entries of the next chunk are loaded ahead; padding repeats the last
+      // slot and is masked out
+      uint32_t e[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) e[u] = k0 + u < k1 ? (uint32_t)row[(size_t)(k0 + u) * stride] : 0u;
+      for (int32_t kk = k0; kk < k1; kk += U) {
+        uint32_t en[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t k = kk + U + u;
+          en[u] = k < k1 ? (uint32_t)row[(size_t)k * stride] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t v = (int32_t)(e[u] & 0x3fffu);
+          double qx, qy, qz;
+          if (v < lcap) {
+            qx = xs[v];
+            qy = ys[v];
+            qz = zs[v];
+          } else {
+            const double4 q = fetch_slot(S, pos, v + base);
+            qx = q.x;
+            qy = q.y;
+            qz = q.z;
+          }
+          const int32_t ab = ti * 4 + (int32_t)(e[u] >> 14);
+          const T dx = (T)(p.x - qx), dy = (T)(p.y - qy), dz = (T)(p.z - qz);
+          const T r2 = dx * dx + dy * dy + dz * dz;
+          if (kk + u < k1 && r2 < P.rc2[ab]) {
+            T rinv;
+            if constexpr (MIXED)
+              rinv = __builtin_amdgcn_rsqf(r2);
+            else
+              rinv = rsqrt_nr(r2);
+            const T r2inv = rinv * rinv;
+            const T sr2 = P.sig2[ab] * r2inv;
+            const T sr6 = sr2 * sr2 * sr2;
+            const T sr12 = sr6 * sr6;
+            const T fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
+            fx += fr * dx;
+            fy += fr * dy;
+            fz += fr * dz;
+            pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
+                    (r2 * rinv - P.rc[ab]) * P.fs[ab];
+            w_i += fr * r2;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) e[u] = en[u];
+      }
+      __syncthreads();  // the next pass overwrites the staged rows
+    }
+    if (mine) {
+      if (!isfinite((double)(fx + fy + fz))) atomicOr(&st->err, kErrNonFinite);
+      T* frc = (T*)frc_;
+      frc[i] = fx;
+      frc[stride + i] = fy;
+      frc[2 * (size_t)stride + i] = fz;
+      pe += 0.5 * (double)pe_i;
+      w += 0.5 * (double)w_i;
+      const double m = s_mass[ti];
+      double v0 = vel[i], v1 = vel[stride + i], v2 = vel[2 * (size_t)stride + i];
+      if (MODE == 1) {
+        const double hm = 0.5 * dt / m;
+        v0 += hm * (double)fx;
+        v1 += hm * (double)fy;
+        v2 += hm * (double)fz;
+        vel[i] = v0;
+        vel[stride + i] = v1;
+        vel[2 * (size_t)stride + i] = v2;
+      }
+      ke += 0.5 * m * (v0 * v0 + v1 * v1 + v2 * v2);
+    }
+  }
+  block_sum3<BT>(pe, w, ke);
+  if (threadIdx.x == 0) {
+    double* o = part + 4 * (size_t)tb;
+    o[0] = pe;
+    o[1] = w;
+    o[2] = ke;
+  }
+}
+
+}  // namespace
+
+size_t force_staged_lds_bytes(int32_t lcap) { return (size_t)lcap * 24; }
+
+void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t bt, int32_t unroll,
+                         int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
+                         const PairTab* tab, const int32_t* cell_start, const double4* pos,
+                         double* vel, void* frc, const uint16_t* nbr, const int32_t* ncount,
+                         const uint32_t* nsplit, int32_t stride, int32_t cap, int32_t lcap,
+                         double dt, double* part, DevState* st) {
+  const size_t lds = force_staged_lds_bytes(lcap);
+#define KS(M, MO, B, UU)                                                                       \
+  k_force_staged<M, MO, B, UU><<<nrt, B, lds, s>>>(rtiles, reps, tab, cell_start, pos, vel, frc, \
+                                                  nbr, ncount, nsplit, stride, cap, lcap, dt,  \
+                                                  part, st)
+#define BYU(M, MO)                                 \
+  do {                                             \
+    if (bt == 128) {                               \
+      if (unroll == 8) KS(M, MO, 128, 8);          \
+      else if (unroll == 2) KS(M, MO, 128, 2);     \
+      else KS(M, MO, 128, 4);                      \
+    } else {                                       \
+      if (unroll == 8) KS(M, MO, 256, 8);          \
+      else if (unroll == 2) KS(M, MO, 256, 2);     \
+      else KS(M, MO, 256, 4);                      \
+    }                                              \
+  } while (0)
+  if (mixed) {
+    if (mode) BYU(true, 1); else BYU(true, 0);
+  } else {
+    if (mode) BYU(false, 1); else BYU(false, 0);
+  }
+#undef BYU
+#undef KS
+}
+
+}  // namespace mdk

@@ -84,7 +84,7 @@ __device__ inline void neumaier(double& s, double& c, double x) {
 // One block per replica: compensated sums of the per-block partials in a
 // fixed order (deterministic), then observables and the thermostat factor.
 __global__ __launch_bounds__(256) void k_reduce(const RepDesc* __restrict__ reps,
-                                                const double* __restrict__ part, int32_t tpp,
+                                                const double* __restrict__ part,
                                                 int32_t step, ThermoArgs ta,
                                                 int64_t* __restrict__ kcall,
                                                 double* __restrict__ lam,
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_reduce(const RepDesc* __restrict__ reps
   const int32_t r = blockIdx.x;
   const RepDesc R = reps[r];
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
-  const int32_t b0 = R.tile0 * tpp, b1 = R.tile1 * tpp;
+  const int32_t b0 = R.fb0, b1 = R.fb1;
   for (int32_t b = b0 + threadIdx.x; b < b1; b += 256)
     for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
   for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
@@ -209,9 +209,9 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
 }
 
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
-                   int32_t tpp, int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
+                   int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
                    int32_t* rebuild, unsigned long long* maxd2, md_obs* obs, DevState* st) {
-  k_reduce<<<nrep, 256, 0, s>>>(reps, part, tpp, step, ta, kcall, lam, rebuild, maxd2, obs, st);
+  k_reduce<<<nrep, 256, 0, s>>>(reps, part, step, ta, kcall, lam, rebuild, maxd2, obs, st);
 }
 
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, unsigned long long* maxd2,

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "md_internal.h"
+#include "stage.h"
 
 using namespace mdk;
 
@@ -17,6 +18,13 @@ struct md_ctx_s {
   md_params p{};
   int32_t nrep = 0, ntot = 0, stride = 0, ncells = 0, ntiles = 0, cap = 0, tpp = 1, unroll = 4;
   int32_t mixed = 0;
+  // staged path (row tiles with LDS-staged neighbourhoods)
+  int32_t staged = 0, bt = 256, nrt = 0, lcap_nl = 0, lcap_f = 0;
+  int32_t any_single = 0, any_multi = 0;  // replicas with one cell / with >= 3 per side
+  std::vector<RowTile> rtiles_h;
+  RowTile* rtiles = nullptr;
+  uint16_t* nbr16 = nullptr;
+  uint32_t* nsplit = nullptr;  // staged path: list lengths of passes 0 and 1
   hipStream_t stream = nullptr;
   std::vector<RepDesc> reps_h;
   std::vector<Tile> tiles_h;
@@ -140,6 +148,12 @@ md_status validate(const md_params* p, std::string* why) {
   if (p->graph_steps < 0) return *why = "graph_steps must be >= 0", MD_EINVAL;
   if (p->unroll != 0 && p->unroll != 1 && p->unroll != 2 && p->unroll != 4 && p->unroll != 8)
     return *why = "unroll must be 0, 1, 2, 4 or 8", MD_EINVAL;
+  if (p->path < MD_PATH_AUTO || p->path > MD_PATH_STAGED) return *why = "unknown path", MD_EINVAL;
+  if (p->tile_threads != 0 && p->tile_threads != 128 && p->tile_threads != 256)
+    return *why = "tile_threads must be 0, 128 or 256", MD_EINVAL;
+  if (p->tile_cells < 0 || p->tile_cells > kMaxRowCells)
+    return *why = "tile_cells must be 0..64", MD_EINVAL;
+  if (p->stage_slots != 0 && p->stage_slots < 64) return *why = "stage_slots must be 0 or >= 64", MD_EINVAL;
   return MD_OK;
 }
 
@@ -170,9 +184,26 @@ void run_chain(md_ctx c) {
                  c->tmp_src);
   launch_cell_gather(s, c->ncells, c->cell_rep, c->rebuild, c->cell_start, c->tmp_src, c->stride,
                      c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp);
-  launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->p.ntypes, c->cell_start,
-               c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
-               c->xref, c->nbr, c->ncount, c->st);
+  if (c->staged)
+    launch_nlist_staged(s, c->bt, c->nrt, c->rtiles, c->reps, c->rebuild, c->tab, c->cell_start,
+                        c->stride, c->cap, c->lcap_nl, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos,
+                        c->vel, c->id, c->xref, c->nbr16, c->ncount, c->nsplit, c->st);
+  else
+    launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->p.ntypes, c->cell_start,
+                 c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
+                 c->xref, c->nbr, c->ncount, c->st, c->ncells, c->cell_rep, c->any_single,
+                 c->any_multi);
+}
+
+void launch_forces(md_ctx c, int32_t mode) {
+  if (c->staged)
+    launch_force_staged(c->stream, c->mixed, mode, c->bt, c->unroll, c->nrt, c->rtiles, c->reps,
+                        c->tab, c->cell_start, c->pos, c->vel, c->frc, c->nbr16, c->ncount,
+                        c->nsplit, c->stride, c->cap, c->lcap_f, c->p.dt, c->part, c->st);
+  else
+    launch_force(c->stream, c->mixed, mode, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps,
+                 c->tab, c->pos, c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt,
+                 c->part, c->st);
 }
 
 md_status grow_capacity(md_ctx c) {
@@ -181,9 +212,16 @@ md_status grow_capacity(md_ctx c) {
   int32_t m = 0;
   for (int32_t v : cnt) m = std::max(m, v);
   int32_t cap = ((m + 16 + 7) / 8) * 8;
-  dfree(c, c->nbr);
-  c->nbr = nullptr;
-  md_status rc = dalloc(c, &c->nbr, (size_t)cap * c->stride);
+  md_status rc;
+  if (c->staged) {
+    dfree(c, c->nbr16);
+    c->nbr16 = nullptr;
+    rc = dalloc(c, &c->nbr16, (size_t)cap * c->stride);
+  } else {
+    dfree(c, c->nbr);
+    c->nbr = nullptr;
+    rc = dalloc(c, &c->nbr, (size_t)cap * c->stride);
+  }
   if (rc) return rc;
   c->cap = cap;
   return MD_OK;
@@ -215,9 +253,8 @@ ThermoArgs no_thermo() {
 }
 
 void launch_forces0(md_ctx c) {
-  launch_force(c->stream, c->mixed, 0, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps, c->tab, c->pos,
-               c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st);
-  launch_reduce(c->stream, c->nrep, c->reps, c->part, c->tpp, 0, no_thermo(), c->kcall, c->lam,
+  launch_forces(c, 0);
+  launch_reduce(c->stream, c->nrep, c->reps, c->part, 0, no_thermo(), c->kcall, c->lam,
                 c->rebuild, c->maxd2, c->obs, c->st);
 }
 
@@ -294,6 +331,70 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
   }
   c->ncells = coff;
   c->ntiles = tile;
+
+  // kernel path: the staged path needs >= 3 cells per side in every replica
+  bool all3 = true;
+  for (const RepDesc& d : c->reps_h) {
+    all3 = all3 && d.nc >= 3;
+    if (d.nc == 1) c->any_single = 1;
+    else c->any_multi = 1;
+  }
+  if (p->path == MD_PATH_STAGED && !all3) {
+    delete c;
+    return fail(nullptr, MD_EINVAL, "the staged path needs >= 3 cells per box side");
+  }
+  c->staged = p->path == MD_PATH_STAGED;
+  c->bt = p->tile_threads ? p->tile_threads : 256;
+  int32_t lds_max = 65536;
+  {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+      lds_max = v;
+    (void)hipGetLastError();
+    lds_max = std::min(lds_max, 65536);  // stay within the default per-block limit
+  }
+  if (c->staged) {
+    double need = 0.0;
+    for (int r = 0; r < nrep; ++r) {
+      RepDesc& d = c->reps_h[r];
+      const int32_t nc = d.nc;
+      const double ppc = (double)d.n / ((double)nc * nc * nc);
+      int32_t cpt = p->tile_cells;
+      if (cpt <= 0) cpt = (int32_t)std::lround(0.8 * c->bt / ppc);
+      cpt = std::max(1, std::min(cpt, std::min(nc, (int32_t)kMaxRowCells)));
+      const int32_t ntr = (nc + cpt - 1) / cpt;
+      d.fb0 = (int32_t)c->rtiles_h.size();
+      int32_t nxmax = 0;
+      for (int32_t row = 0; row < nc * nc; ++row)
+        for (int32_t t = 0; t < ntr; ++t) {
+          RowTile rt{};
+          rt.rep = r;
+          rt.row = row;
+          rt.a = (int32_t)((int64_t)t * nc / ntr);
+          rt.nx = (int32_t)((int64_t)(t + 1) * nc / ntr) - rt.a;
+          nxmax = std::max(nxmax, rt.nx);
+          c->rtiles_h.push_back(rt);
+        }
+      d.fb1 = (int32_t)c->rtiles_h.size();
+      need = std::max(need, 3.0 * (nxmax + 2) * ppc);  // one pass: 3 rows
+    }
+    c->nrt = (int32_t)c->rtiles_h.size();
+    const int32_t want = (int32_t)((int64_t)std::ceil(1.3 * need + 64) / 64 * 64);
+    const int32_t room = lds_max - 8192;  // static LDS of the kernels
+    c->lcap_f = std::max(64, std::min(want, (int32_t)(room / 24)));
+    c->lcap_nl = std::max(64, std::min(want, (int32_t)(room / 25)));
+    if (p->stage_slots > 0) {
+      c->lcap_f = std::min(c->lcap_f, p->stage_slots);
+      c->lcap_nl = std::min(c->lcap_nl, p->stage_slots);
+    }
+  } else {
+    for (RepDesc& d : c->reps_h) {
+      d.fb0 = d.tile0 * c->tpp;
+      d.fb1 = d.tile1 * c->tpp;
+    }
+  }
   if (p->max_neighbors > 0) {
     c->cap = p->max_neighbors;
   } else {
@@ -375,9 +476,15 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
   ALLOC(c->id, N);
   ALLOC(c->id_tmp, N);
   ALLOC(c->img, 3 * N);
-  ALLOC(c->nbr, (size_t)c->cap * S);
+  if (c->staged) {
+    ALLOC(c->nbr16, (size_t)c->cap * S);
+    ALLOC(c->nsplit, N);
+    ALLOC(c->rtiles, (size_t)c->nrt);
+  } else {
+    ALLOC(c->nbr, (size_t)c->cap * S);
+  }
   ALLOC(c->ncount, N);
-  ALLOC(c->part, 4 * (size_t)c->ntiles * 8);
+  ALLOC(c->part, 4 * std::max((size_t)c->ntiles * 8, (size_t)c->nrt));
   ALLOC(c->rebuild, (size_t)nrep);
   ALLOC(c->maxd2, (size_t)nrep);
   ALLOC(c->obs, (size_t)nrep);
@@ -394,6 +501,7 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
             up(c->tab, &tab, sizeof(PairTab)) &&
             up(c->cell_rep, cell_rep.data(), sizeof(int32_t) * c->ncells) &&
             up(c->lam, ones.data(), sizeof(double) * nrep) &&
+            (!c->staged || up(c->rtiles, c->rtiles_h.data(), sizeof(RowTile) * c->nrt)) &&
             hipMemset(c->st, 0, sizeof(DevState)) == hipSuccess &&
             hipMemset(c->counts, 0, sizeof(int32_t) * c->ncells) == hipSuccess &&
             hipMemset(c->rebuild, 0, sizeof(int32_t) * nrep) == hipSuccess &&
@@ -538,14 +646,13 @@ md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
       }
       HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
     }
-    launch_force(s, c->mixed, 1, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->vel,
-                 c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st);
+    launch_forces(c, 1);
     if (timed) {
       HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
       c->ev_used += 2;
     }
-    launch_reduce(s, c->nrep, c->reps, c->part, c->tpp, 1, ta, c->kcall, c->lam, c->rebuild,
-                  c->maxd2, c->obs, c->st);
+    launch_reduce(s, c->nrep, c->reps, c->part, 1, ta, c->kcall, c->lam, c->rebuild, c->maxd2,
+                  c->obs, c->st);
   }
   if (thermo) launch_apply_lambda(s, c->ntiles, c->tiles, c->stride, c->vel, c->lam, c->nrep);
   HIPCHECK(c, hipGetLastError());
@@ -610,10 +717,23 @@ md_status md_get_neighbors(md_ctx c, int32_t rep, int32_t* count, int32_t* ids, 
   HIPCHECK(c, hipMemcpy(idv.data(), c->id, sizeof(int32_t) * c->ntot, hipMemcpyDeviceToHost));
   const int32_t rows = std::min(c->cap, cap);
   std::vector<uint32_t> ell((size_t)std::max(rows, 1) * d.n);
-  if (rows > 0)
-    HIPCHECK(c, hipMemcpy2D(ell.data(), sizeof(uint32_t) * d.n, c->nbr + d.off,
-                            sizeof(uint32_t) * c->stride, sizeof(uint32_t) * d.n, rows,
-                            hipMemcpyDeviceToHost));
+  if (rows > 0) {
+    const uint32_t* src = c->nbr;
+    uint32_t* tmp = nullptr;
+    if (c->staged) {
+      // staged entries are LDS slots of the home tile: decode to particle indices
+      md_status a_rc = dalloc(c, &tmp, (size_t)rows * c->stride);
+      if (a_rc) return a_rc;
+      launch_decode_staged(c->stream, c->nrt, c->rtiles, c->reps, c->cell_start, c->stride, rows,
+                           c->nbr16, c->ncount, c->nsplit, tmp);
+      src = tmp;
+    }
+    hipError_t e = hipMemcpy2D(ell.data(), sizeof(uint32_t) * d.n, src + d.off,
+                               sizeof(uint32_t) * c->stride, sizeof(uint32_t) * d.n, rows,
+                               hipMemcpyDeviceToHost);
+    if (tmp) dfree(c, tmp);
+    if (e != hipSuccess) return fail(c, MD_EHIP, "hipMemcpy2D of the neighbour list failed");
+  }
   for (int32_t i = 0; i < d.n; ++i) {
     const int32_t orig = idv[d.off + i] - d.off;
     count[orig] = cnt[i];

@@ -52,6 +52,7 @@ struct RepDesc {       // per-replica geometry, device resident
   int32_t off, n;      // particle range
   int32_t coff, nc;    // first cell, cells per side
   int32_t tile0, tile1;// tiles [tile0, tile1)
+  int32_t fb0, fb1;    // force-kernel partial blocks [fb0, fb1) of this replica
 };
 
 // Per species pair ab = a * 4 + b.  The pair function Eq. (3) is written as
@@ -119,7 +120,8 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   const int32_t* cell_start, int32_t stride, int32_t cap,
                   const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                   double4* pos, double* vel, int32_t* id, double* xref,
-                  uint32_t* nbr, int32_t* ncount, DevState* st);
+                  uint32_t* nbr, int32_t* ncount, DevState* st, int32_t ncells,
+                  const int32_t* cell_rep, int32_t any_single, int32_t any_multi);
 // force.hip
 // mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
 // half kick v += dt/2 F/m before KE.
@@ -147,14 +149,35 @@ struct ThermoArgs {
 };
 // step = 0: observables of the current state only; step = 1: end of a step
 // part holds one (pe, w, ke) triple per force block; replica r owns blocks
-// [tile0 * tpp, tile1 * tpp).
+// [fb0, fb1).
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
-                   int32_t tpp, int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
+                   int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
                    int32_t* rebuild, unsigned long long* maxd2, md_obs* obs, DevState* st);
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild,
                         unsigned long long* maxd2, md_obs* obs, DevState* st);
 void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam);
 void launch_apply_lambda(hipStream_t s, int32_t ntiles, const Tile* tiles, int32_t stride,
                          double* vel, double* lam, int32_t nrep);
+
+// staged path (stage.h, nlist_staged.hip, force_staged.hip)
+struct RowTile;
+size_t nlist_staged_lds_bytes(int32_t lcap);
+size_t force_staged_lds_bytes(int32_t lcap);
+void launch_nlist_staged(hipStream_t s, int32_t bt, int32_t nrt, const RowTile* rtiles,
+                         const RepDesc* reps, const int32_t* rebuild, const PairTab* tab,
+                         const int32_t* cell_start, int32_t stride, int32_t cap, int32_t lcap,
+                         const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
+                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr,
+                         int32_t* ncount, uint32_t* nsplit, DevState* st);
+void launch_decode_staged(hipStream_t s, int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
+                          const int32_t* cell_start, int32_t stride, int32_t rows,
+                          const uint16_t* nbr, const int32_t* ncount, const uint32_t* nsplit,
+                          uint32_t* out);
+void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t bt, int32_t unroll,
+                         int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
+                         const PairTab* tab, const int32_t* cell_start, const double4* pos,
+                         double* vel, void* frc, const uint16_t* nbr, const int32_t* ncount,
+                         const uint32_t* nsplit, int32_t stride, int32_t cap, int32_t lcap,
+                         double dt, double* part, DevState* st);
 
 }  // namespace mdk

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
     const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
     const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
     int32_t* __restrict__ id, double* __restrict__ xref, uint32_t* __restrict__ nbr,
-    int32_t* __restrict__ ncount, DevState* st) {
+    int32_t* __restrict__ ncount, DevState* st, int32_t skip_multi) {
   __shared__ double s_thr[16];
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
   const int32_t i = t.start + threadIdx.x;
   if (i >= t.end) return;
   const RepDesc R = reps[t.rep];
+  if (R.nc != 1 && skip_multi) return;  // handled by k_nlist_cells
   const double4 p = pos_tmp[i];
   const int32_t ti = (int32_t)p.w;
   const double* thr = &s_thr[ti * 4];
@@ -82,6 +83,8 @@ __global__ __launch_bounds__(kTile) void k_nlist(
       }
     }
   } else {
+    // 9 neighbour rows; along x the cells cx-1 .. cx+1 of a row are one
+    // contiguous range unless the row wraps, then up to three ranges
     const int32_t nc = R.nc;
     const int32_t qx = cell_coord(p.x, R.inv_cell, nc);
     const int32_t qy = cell_coord(p.y, R.inv_cell, nc);
@@ -94,21 +97,55 @@ __global__ __launch_bounds__(kTile) void k_nlist(
         int32_t ny, sy;
         stencil_axis(qy, oy, nc, ny, sy);
         const double shy = (double)sy * R.L;
-        for (int32_t ox = -1; ox <= 1; ++ox) {
-          int32_t nx, sx;
-          stencil_axis(qx, ox, nc, nx, sx);
-          const double shx = (double)sx * R.L;
-          const uint32_t code = image_code(sx, sy, sz);
-          const int32_t cn = R.coff + (nz * nc + ny) * nc + nx;
-          const int32_t k1 = cell_start[cn + 1];
-          for (int32_t k = cell_start[cn]; k < k1; ++k) {
-            if (k == i) continue;
+        const int32_t rowbase = R.coff + (nz * nc + ny) * nc;
+        int32_t r0[3], r1[3], rs[3];
+        int nr = 0;
+        if (qx - 1 < 0) {
+          r0[nr] = cell_start[rowbase + nc - 1];
+          r1[nr] = cell_start[rowbase + nc];
+          rs[nr++] = -1;
+        }
+        {
+          const int32_t lo = qx - 1 < 0 ? 0 : qx - 1;
+          const int32_t hi = qx + 1 >= nc ? nc - 1 : qx + 1;
+          r0[nr] = cell_start[rowbase + lo];
+          r1[nr] = cell_start[rowbase + hi + 1];
+          rs[nr++] = 0;
+        }
+        if (qx + 1 >= nc) {
+          r0[nr] = cell_start[rowbase];
+          r1[nr] = cell_start[rowbase + 1];
+          rs[nr++] = 1;
+        }
+        for (int m = 0; m < nr; ++m) {
+          const double shx = (double)rs[m] * R.L;
+          const uint32_t code = image_code(rs[m], sy, sz);
+          int32_t k = r0[m];
+          const int32_t k1 = r1[m];
+          // four candidates per iteration keep four gathers in flight
+          for (; k + 4 <= k1; k += 4) {
+            double4 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = pos_tmp[k + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const double ex = (q[u].x + shx) - p.x;
+              const double ey = (q[u].y + shy) - p.y;
+              const double ez = (q[u].z + shz) - p.z;
+              const double r2 = (ex * ex + ey * ey) + ez * ez;
+              if (k + u != i && r2 < thr[(int32_t)q[u].w]) {
+                if (cnt < cap) out[(size_t)cnt * stride] = (uint32_t)(k + u) | code;
+                ++cnt;
+              }
+            }
+          }
+          for (; k < k1; ++k) {
             const double4 q = pos_tmp[k];
-            double ex = (q.x + shx) - p.x;
-            double ey = (q.y + shy) - p.y;
-            double ez = (q.z + shz) - p.z;
-            double r2 = (ex * ex + ey * ey) + ez * ez;
-            if (r2 < thr[(int32_t)q.w]) {
+            const double ex = (q.x + shx) - p.x;
+            const double ey = (q.y + shy) - p.y;
+            const double ez = (q.z + shz) - p.z;
+            const double r2 = (ex * ex + ey * ey) + ez * ez;
+            if (k != i && r2 < thr[(int32_t)q.w]) {
               if (cnt < cap) out[(size_t)cnt * stride] = (uint32_t)k | code;
               ++cnt;
             }
@@ -131,6 +168,165 @@ __global__ __launch_bounds__(kTile) void k_nlist(
   (void)ntypes;
 }
 
+
+// One wave per home cell (nc >= 3).  The candidates of the cell -- the 9
+// neighbour rows, each one to three contiguous particle ranges with their
+// periodic shift -- are packed 64 to a chunk, one candidate per lane, with
+// x_j + s L formed once per chunk.  For every home particle (uniform loop,
+// coordinates through scalar loads) each lane tests its candidate; the hits
+// are compacted with a ballot and appended to the home particle's row in
+// candidate order.  Copying the new order into the live arrays is done here
+// as well.
+constexpr int kCwGroup = 64;  // home particles per pass: lane h keeps the count of home h
+
+// Test the lane's candidate against home particle ih (wave-uniform) and append
+// the hits to that particle's row; cnt is the particle's running count.
+__device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_t ih,
+                                    uint32_t entry, int32_t cap, int32_t stride,
+                                    uint32_t* __restrict__ nbr) {
+  if (mask) {
+    const int32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+    if (hit && cnt + rk < cap) nbr[(size_t)(cnt + rk) * stride + ih] = entry;
+    cnt += (int32_t)__popcll(mask);
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(256) void k_nlist_cells(
+    int32_t ncells, const int32_t* __restrict__ cell_rep, const RepDesc* __restrict__ reps,
+    const int32_t* __restrict__ rebuild, const PairTab* __restrict__ tab,
+    const int32_t* __restrict__ cell_start, int32_t stride, int32_t cap,
+    const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
+    const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
+    int32_t* __restrict__ id, double* __restrict__ xref, uint32_t* __restrict__ nbr,
+    int32_t* __restrict__ ncount, DevState* st) {
+  __shared__ double s_thr[16];
+  __shared__ int32_t s_pre[4][28];    // first packed candidate of piece p
+  __shared__ int32_t s_k0[4][27];     // first sorted index of piece p
+  __shared__ int32_t s_code[4][27];   // image code of piece p (shift -1/0/1 per axis)
+  if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t c = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+  if (c >= ncells) return;
+  const int32_t r = cell_rep[c];
+  if (!rebuild[r]) return;
+  const RepDesc R = reps[r];
+  if (R.nc == 1) return;  // minimum-image kernel
+  const int32_t nc = R.nc;
+  const int32_t lc = c - R.coff;
+  const int32_t qx = lc % nc, qy = (lc / nc) % nc, qz = lc / (nc * nc);
+  const int32_t h0 = cell_start[c], nh = cell_start[c + 1] - h0;
+
+  // pieces: lane q < 9 builds neighbour row q (dz = q/3 - 1, dy = q%3 - 1)
+  if (lane < 9) {
+    int32_t nz, sz, ny, sy;
+    stencil_axis(qz, lane / 3 - 1, nc, nz, sz);
+    stencil_axis(qy, lane % 3 - 1, nc, ny, sy);
+    const int32_t rowbase = R.coff + (nz * nc + ny) * nc;
+    const int p = 3 * lane;
+    // left wrap, main, right wrap; empty pieces have zero length
+    s_k0[w][p] = cell_start[rowbase + nc - 1];
+    s_code[w][p] = (int32_t)image_code(-1, sy, sz);
+    const int32_t nl = qx - 1 < 0 ? cell_start[rowbase + nc] - cell_start[rowbase + nc - 1] : 0;
+    const int32_t lo = qx - 1 < 0 ? 0 : qx - 1, hi = qx + 1 >= nc ? nc - 1 : qx + 1;
+    s_k0[w][p + 1] = cell_start[rowbase + lo];
+    s_code[w][p + 1] = (int32_t)image_code(0, sy, sz);
+    const int32_t nm = cell_start[rowbase + hi + 1] - cell_start[rowbase + lo];
+    s_k0[w][p + 2] = cell_start[rowbase];
+    s_code[w][p + 2] = (int32_t)image_code(1, sy, sz);
+    const int32_t nr = qx + 1 >= nc ? cell_start[rowbase + 1] - cell_start[rowbase] : 0;
+    s_pre[w][p] = nl;  // lengths for now
+    s_pre[w][p + 1] = nm;
+    s_pre[w][p + 2] = nr;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) {
+    int32_t acc = 0;
+    for (int p = 0; p < 27; ++p) {
+      const int32_t len = s_pre[w][p];
+      s_pre[w][p] = acc;
+      acc += len;
+    }
+    s_pre[w][27] = acc;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int32_t ncand = s_pre[w][27];
+
+  for (int32_t g0 = 0; g0 < nh; g0 += kCwGroup) {
+    const int32_t gn = nh - g0 < kCwGroup ? nh - g0 : kCwGroup;
+    const int32_t gbase = h0 + g0;
+    int32_t cntv = 0;  // lane h: neighbours found so far for home gbase + h
+    for (int32_t base = 0; base < ncand; base += 64) {
+      const int32_t v = base + lane;
+      const bool valid = v < ncand;
+      int p = 0;
+      for (int q = 1; q < 27; ++q)
+        if (s_pre[w][q] <= v) p = q;
+      const int32_t k = valid ? s_k0[w][p] + (v - s_pre[w][p]) : h0;
+      const uint32_t code = (uint32_t)s_code[w][p];
+      const double4 q = pos_tmp[k];
+      // the periodic shift of the piece: x_j + s L
+      const double sx = (double)(((int32_t)(code << 4)) >> 30) * R.L;
+      const double sy = (double)(((int32_t)(code << 2)) >> 30) * R.L;
+      const double sz = (double)(((int32_t)code) >> 30) * R.L;
+      const double xs = q.x + sx, ys = q.y + sy, zs = q.z + sz;
+      const double* thr = &s_thr[(int32_t)q.w];  // thr[4 * ti] is the pair (ti, tj)
+      const uint32_t entry = (uint32_t)k | code;
+      int32_t h = 0;
+      // two home particles per iteration (wave-uniform, scalar loads)
+      for (; h + 2 <= gn; h += 2) {
+        const int32_t ia = __builtin_amdgcn_readfirstlane(gbase + h);
+        const int32_t ib = ia + 1;
+        const double4 pa = pos_tmp[ia];
+        const double4 pb = pos_tmp[ib];
+        const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
+        const double bx = xs - pb.x, by = ys - pb.y, bz = zs - pb.z;
+        const double ra = (ax * ax + ay * ay) + az * az;
+        const double rb = (bx * bx + by * by) + bz * bz;
+        const bool hita = (int)valid & (int)(k != ia) & (int)(ra < thr[4 * (int32_t)pa.w]);
+        const bool hitb = (int)valid & (int)(k != ib) & (int)(rb < thr[4 * (int32_t)pb.w]);
+        const uint64_t ma = __ballot(hita), mb = __ballot(hitb);
+        int32_t ca = __builtin_amdgcn_readlane(cntv, h);
+        int32_t cb = __builtin_amdgcn_readlane(cntv, h + 1);
+        ca = cw_append(ma, hita, ca, ia, entry, cap, stride, nbr);
+        cb = cw_append(mb, hitb, cb, ib, entry, cap, stride, nbr);
+        cntv = lane == h ? ca : cntv;
+        cntv = lane == h + 1 ? cb : cntv;
+      }
+      if (h < gn) {
+        const int32_t ia = __builtin_amdgcn_readfirstlane(gbase + h);
+        const double4 pa = pos_tmp[ia];
+        const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
+        const double ra = (ax * ax + ay * ay) + az * az;
+        const bool hita = (int)valid & (int)(k != ia) & (int)(ra < thr[4 * (int32_t)pa.w]);
+        const uint64_t ma = __ballot(hita);
+        int32_t ca = __builtin_amdgcn_readlane(cntv, h);
+        ca = cw_append(ma, hita, ca, ia, entry, cap, stride, nbr);
+        cntv = lane == h ? ca : cntv;
+      }
+    }
+    if (lane < gn) {
+      ncount[gbase + lane] = cntv;
+      if (cntv > cap) atomicOr(&st->err, kErrOverflow);
+    }
+  }
+  // the new cell order becomes the live state
+  for (int32_t h = lane; h < nh; h += 64) {
+    const int32_t i = h0 + h;
+    const double4 p4 = pos_tmp[i];
+    pos[i] = p4;
+    xref[i] = p4.x;
+    xref[stride + i] = p4.y;
+    xref[2 * (size_t)stride + i] = p4.z;
+    vel[i] = vel_tmp[i];
+    vel[stride + i] = vel_tmp[stride + i];
+    vel[2 * (size_t)stride + i] = vel_tmp[2 * (size_t)stride + i];
+    id[i] = id_tmp[i];
+  }
+}
+
 }  // namespace
 
 void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
@@ -138,10 +334,16 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   const int32_t* cell_start, int32_t stride, int32_t cap,
                   const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                   double4* pos, double* vel, int32_t* id, double* xref, uint32_t* nbr,
-                  int32_t* ncount, DevState* st) {
-  k_nlist<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, tab, ntypes, cell_start, stride, cap,
-                                   pos_tmp, vel_tmp, id_tmp, pos, vel, id, xref, nbr, ncount,
-                                   st);
+                  int32_t* ncount, DevState* st, int32_t ncells, const int32_t* cell_rep,
+                  int32_t any_single, int32_t any_multi) {
+  if (any_multi)
+    k_nlist_cells<<<(ncells + 3) / 4, 256, 0, s>>>(ncells, cell_rep, reps, rebuild, tab,
+                                                   cell_start, stride, cap, pos_tmp, vel_tmp,
+                                                   id_tmp, pos, vel, id, xref, nbr, ncount, st);
+  if (any_single)
+    k_nlist<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, tab, ntypes, cell_start, stride, cap,
+                                     pos_tmp, vel_tmp, id_tmp, pos, vel, id, xref, nbr, ncount,
+                                     st, 1);
 }
 
 }  // namespace mdk

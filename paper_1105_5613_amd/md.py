@@ -21,6 +21,7 @@ MD_OK, MD_EINVAL, MD_ENOMEM, MD_EBOX, MD_EOVERFLOW, MD_ENONFINITE, MD_EHIP, MD_E
 MD_FP64, MD_MIXED = 0, 1
 MD_POT_LJ, MD_POT_SOFT = 0, 1
 MD_TRUNC_SHIFTED_FORCE, MD_TRUNC_SHIFT = 0, 1
+MD_PATH_AUTO, MD_PATH_GATHER, MD_PATH_STAGED = 0, 1, 2
 
 EXPORTS = ["md_init", "md_destroy", "md_last_error", "md_set_state", "md_get_state",
            "md_build_cells", "md_forces", "md_get_forces", "md_step", "md_observables",
@@ -39,7 +40,9 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("eps", C.c_double * 16), ("sig", C.c_double * 16),
                 ("rc", C.c_double * 16), ("mass", C.c_double * 4), ("skin", C.c_double),
                 ("dt", C.c_double), ("max_neighbors", C.c_int32), ("graph_steps", C.c_int32),
-                ("tpp", C.c_int32), ("unroll", C.c_int32)]
+                ("tpp", C.c_int32), ("unroll", C.c_int32),
+                ("path", C.c_int32), ("tile_threads", C.c_int32), ("tile_cells", C.c_int32),
+                ("stage_slots", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -97,7 +100,8 @@ def lib():
 
 def make_params(eps, sig, rc, mass, *, skin=0.3, dt=0.005, precision=MD_FP64,
                 potential=MD_POT_LJ, trunc=MD_TRUNC_SHIFTED_FORCE, max_neighbors=0,
-                graph_steps=0, tpp=0, unroll=0) -> Params:
+                graph_steps=0, tpp=0, unroll=0, path=MD_PATH_AUTO, tile_threads=0,
+                tile_cells=0, stage_slots=0) -> Params:
     p = Params()
     nt = len(eps)
     p.ntypes = nt
@@ -116,6 +120,10 @@ def make_params(eps, sig, rc, mass, *, skin=0.3, dt=0.005, precision=MD_FP64,
     p.graph_steps = int(graph_steps)
     p.tpp = int(tpp)
     p.unroll = int(unroll)
+    p.path = int(path)
+    p.tile_threads = int(tile_threads)
+    p.tile_cells = int(tile_cells)
+    p.stage_slots = int(stage_slots)
     return p
 
 

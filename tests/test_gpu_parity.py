@@ -49,10 +49,22 @@ def compare_cells_lists(sysm, p, x, types, L, rep=0, tag=""):
     return xw, count, ids
 
 
-@pytest.mark.parametrize("n,seed", [(4000, 1), (32000, 7), (500, 3)])
-def test_cells_lists_forces_fp64(torch_cuda, n, seed):
-    say(f"case cells/lists/forces fp64 n={n} seed={seed}")
-    sysm, s = make_system(torch_cuda, n, seed)
+PATHS = {"gather": dict(path=1), "staged": dict(path=2)}
+
+
+@pytest.mark.parametrize("n,seed,kw", [
+    (4000, 1, PATHS["gather"]), (4000, 1, PATHS["staged"]),
+    (32000, 7, PATHS["gather"]), (32000, 7, PATHS["staged"]),
+    (500, 3, {}),
+    (32000, 8, dict(path=2, tile_cells=1)),                  # one home cell per tile
+    (32000, 9, dict(path=2, tile_cells=64)),                 # whole rows: both wrap pieces
+    (32000, 10, dict(path=2, stage_slots=256)),              # most slots from global memory
+    (13500, 11, dict(path=2, tile_threads=128, unroll=8)),
+], ids=["4k-gather", "4k-staged", "32k-gather", "32k-staged", "500-onecell", "32k-cell1",
+        "32k-row", "32k-slots256", "13.5k-bt128"])
+def test_cells_lists_forces_fp64(torch_cuda, n, seed, kw):
+    say(f"case cells/lists/forces fp64 n={n} seed={seed} {kw}")
+    sysm, s = make_system(torch_cuda, n, seed, **kw)
     p = oracle_params()
     sysm.build_cells()
     xw, count, ids = compare_cells_lists(sysm, p, s["x"], s["type"], s["L"], tag=f"n={n}")
@@ -72,9 +84,10 @@ def test_cells_lists_forces_fp64(torch_cuda, n, seed):
     assert ob["n_rebuild"] == 1
 
 
-def test_forces_mixed(torch_cuda):
-    say("case forces mixed n=32000")
-    sysm, s = make_system(torch_cuda, 32000, 7, precision=1)
+@pytest.mark.parametrize("path", ["gather", "staged"])
+def test_forces_mixed(torch_cuda, path):
+    say(f"case forces mixed n=32000 {path}")
+    sysm, s = make_system(torch_cuda, 32000, 7, precision=1, **PATHS[path])
     p = oracle_params()
     sysm.forces()
     F = sysm.get_forces().cpu().numpy()
@@ -88,11 +101,12 @@ def test_forces_mixed(torch_cuda):
     assert ob["virial"] == pytest.approx(w_i.sum(), rel=1e-6)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_states_after_steps(torch_cuda, precision):
+@pytest.mark.parametrize("precision,path", [(0, "gather"), (0, "staged"), (1, "gather"),
+                                            (1, "staged")])
+def test_states_after_steps(torch_cuda, precision, path):
     """Cells, lists and forces re-checked on states reached by stepping."""
-    say(f"case stepped states precision={precision}")
-    sysm, s = make_system(torch_cuda, 4000, 1, precision=precision)
+    say(f"case stepped states precision={precision} {path}")
+    sysm, s = make_system(torch_cuda, 4000, 1, precision=precision, **PATHS[path])
     p = oracle_params()
     done = 0
     for target in (10, 50, 100):
@@ -130,11 +144,12 @@ def test_short_trajectory_matches_oracle(torch_cuda):
     assert np.array_equal(log["step"][:, 0], np.arange(1, 21))
 
 
-def test_nve_drift_fp64_and_mixed(torch_cuda):
+@pytest.mark.parametrize("path", ["gather", "staged"])
+def test_nve_drift_fp64_and_mixed(torch_cuda, path):
     """4,000 particles, dt = 0.005: steady-state drift below 1e-4 per particle."""
     for precision in (0, 1):
-        say(f"case drift precision={precision}")
-        sysm, s = make_system(torch_cuda, 4000, 1, precision=precision)
+        say(f"case drift precision={precision} {path}")
+        sysm, s = make_system(torch_cuda, 4000, 1, precision=precision, **PATHS[path])
         log = sysm.step(1100, log_every=1)
         D = drift_slope(log["E"][:, 0], 4000)
         say(f"  drift D = {D:.3e}, rebuilds = {log['n_rebuild'][-1, 0]}")
@@ -175,8 +190,13 @@ def test_batched_replicas(torch_cuda):
     temps = [0.4, 1.0, 2.0, 1.5, 0.7]
     systems = initconf.batched_systems(sizes, temps, seed=9)
     x, v, t, n, L = initconf.concat_replicas(systems)
-    for precision in (0, 1):
-        sysm = System(lib_params(precision=precision), n, L)
+    for precision, kw in ((0, {}), (1, {}), (0, dict(path=2))):
+        if kw:   # every replica with >= 3 cells per side: the staged path
+            keep = [r for r, sy in enumerate(systems) if sy["L"] >= 3 * 2.8]
+            systems = [systems[r] for r in keep]
+            temps = [temps[r] for r in keep]
+            x, v, t, n, L = initconf.concat_replicas(systems)
+        sysm = System(lib_params(precision=precision, **kw), n, L)
         sysm.set_state(x, v, t)
         sysm.build_cells()
         sysm.forces()
@@ -232,12 +252,13 @@ def test_error_paths(torch_cuda):
     compare_cells_lists(small, p, s["x"], s["type"], s["L"], tag="grown capacity")
 
 
-def test_large_box_sampled(torch_cuda):
+@pytest.mark.parametrize("path", ["gather", "staged"])
+def test_large_box_sampled(torch_cuda, path):
     """1,048,576 particles: full lists bit-exact, sampled forces vs the oracle."""
-    say("case 1M particles")
+    say(f"case 1M particles {path}")
     n = 1048576
     for precision in (0, 1):
-        sysm, s = make_system(torch_cuda, n, 2, precision=precision)
+        sysm, s = make_system(torch_cuda, n, 2, precision=precision, **PATHS[path])
         p = oracle_params()
         sysm.step(20)
         x, v, img = sysm.get_state()
@@ -259,12 +280,13 @@ def test_large_box_sampled(torch_cuda):
             (1e-9 if precision == 0 else 1e-2) * np.sum(Fall)
 
 
-def test_deterministic(torch_cuda):
+@pytest.mark.parametrize("path", ["gather", "staged"])
+def test_deterministic(torch_cuda, path):
     """Two runs from the same state give identical bits (fixed reduction order)."""
-    say("case determinism")
+    say(f"case determinism {path}")
     outs = []
     for _ in range(2):
-        sysm, s = make_system(torch_cuda, 32000, 7)
+        sysm, s = make_system(torch_cuda, 32000, 7, **PATHS[path])
         log = sysm.step(30, log_every=1)
         x, v, img = sysm.get_state()
         outs.append((x.cpu().numpy(), v.cpu().numpy(), log["E"]))
