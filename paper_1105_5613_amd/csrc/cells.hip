@@ -110,6 +110,10 @@ __device__ inline int32_t cell_coord(double c, double inv_cell, int32_t nc) {
   return q > nc - 1 ? nc - 1 : q;
 }
 
+// Wrap + bin.  Particles arrive in the cell order of the previous build, so
+// the lanes of a wave form a few runs of equal cell: one atomic per run
+// reserves the run's slots (the in-cell order is fixed later by the rank
+// sort, so slot order does not matter).
 __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
                                                const RepDesc* __restrict__ reps,
                                                const int32_t* __restrict__ rebuild,
@@ -121,28 +125,47 @@ __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
                                                int32_t* __restrict__ slot, DevState* st) {
   const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   if (!rebuild[t.rep]) return;
+  const int lane = threadIdx.x & 63;
   const int32_t i = t.start + threadIdx.x;
-  if (i >= t.end) return;
+  const int32_t wave0 = t.start + (int32_t)(threadIdx.x & ~63u);
+  if (wave0 >= t.end) return;  // whole wave past the tile
+  const bool active = i < t.end;
   const RepDesc R = reps[t.rep];
-  double4 p = pos[i];
-  int32_t bad = 0;
-  int32_t dx = wrap1(p.x, R.L, bad);
-  int32_t dy = wrap1(p.y, R.L, bad);
-  int32_t dz = wrap1(p.z, R.L, bad);
-  if (bad) latch(st, kErrStray);
-  if (dx | dy | dz) {
-    size_t o = 3 * (size_t)id[i];
-    img[o] += dx;
-    img[o + 1] += dy;
-    img[o + 2] += dz;
+  int32_t c = -1;
+  if (active) {
+    double4 p = pos[i];
+    int32_t bad = 0;
+    int32_t dx = wrap1(p.x, R.L, bad);
+    int32_t dy = wrap1(p.y, R.L, bad);
+    int32_t dz = wrap1(p.z, R.L, bad);
+    if (bad) latch(st, kErrStray);
+    if (dx | dy | dz) {
+      size_t o = 3 * (size_t)id[i];
+      img[o] += dx;
+      img[o + 1] += dy;
+      img[o + 2] += dz;
+    }
+    pos[i] = p;
+    int32_t qx = cell_coord(p.x, R.inv_cell, R.nc);
+    int32_t qy = cell_coord(p.y, R.inv_cell, R.nc);
+    int32_t qz = cell_coord(p.z, R.inv_cell, R.nc);
+    c = R.coff + (qz * R.nc + qy) * R.nc + qx;
+    cell_of[i] = c;
   }
-  pos[i] = p;
-  int32_t qx = cell_coord(p.x, R.inv_cell, R.nc);
-  int32_t qy = cell_coord(p.y, R.inv_cell, R.nc);
-  int32_t qz = cell_coord(p.z, R.inv_cell, R.nc);
-  int32_t c = R.coff + (qz * R.nc + qy) * R.nc + qx;
-  cell_of[i] = c;
-  slot[i] = atomicAdd(&counts[c], 1);
+  // runs of equal cell among consecutive active lanes
+  const int32_t cp = __shfl_up(c, 1, 64);
+  const bool lead = active && (lane == 0 || cp != c);
+  const uint64_t leaders = __ballot(lead);
+  const uint64_t act = __ballot(active);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int my_lead = 63 - __builtin_clzll((leaders & upto) | 1ull);
+  const uint64_t after = my_lead == 63 ? 0ull : (leaders >> (my_lead + 1));
+  const int n_act = __popcll(act);
+  const int next = after ? my_lead + 1 + __builtin_ctzll(after) : n_act;
+  int32_t base = 0;
+  if (lead) base = atomicAdd(&counts[c], next - my_lead);
+  base = __shfl(base, my_lead, 64);
+  if (active) slot[i] = base + (lane - my_lead);
 }
 
 // ---- exclusive scan of the cell counts ------------------------------------------

@@ -6,9 +6,12 @@
 // FP64 form: everything in double; 1/r from an FP32 reciprocal-square-root
 // seed refined by two Newton-Raphson steps y <- y (3 - r^2 y^2) / 2, the
 // scheme the paper uses on BlueGene/P ("BlueGene specific optimizations").
-// Mixed form: the displacement is formed in FP64 from the FP64 positions,
-// then rounded to FP32; pair arithmetic and the per-particle force sum are
-// FP32; per-particle energy/virial are widened to FP64 for the reductions.
+// Mixed form: neighbours are gathered as 16-byte FP32 records relative to
+// their build-time cell centre (make_rec16), from which the displacement is
+// formed in FP32 with an absolute error of a few 1e-7 (half the bytes of the
+// FP64 records, so half the cache-line requests); pair arithmetic and the
+// per-particle force sum are FP32; per-particle energy/virial are widened to
+// FP64 for the reductions.
 //
 // One thread per particle (tpp = 1) walks its ELL row; threads per particle
 // tpp in {2, 4, 8} split the row into interleaved slots and combine their
@@ -89,9 +92,10 @@ __device__ inline void block_sum3(double& a, double& b, double& c) {
 template <bool MIXED, int MODE, int TPP, int U>
 __global__ __launch_bounds__(kTile) void k_force(
     const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
-    const PairTab* __restrict__ tab, const double4* __restrict__ pos, double* __restrict__ vel,
-    void* __restrict__ frc_, const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncount,
-    int32_t stride, int32_t cap, double dt, double* __restrict__ part, DevState* st) {
+    const PairTab* __restrict__ tab, const double4* __restrict__ pos,
+    const float4* __restrict__ pos16, double* __restrict__ vel, void* __restrict__ frc_,
+    const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncount, int32_t stride,
+    int32_t cap, double dt, double* __restrict__ part, DevState* st) {
   using T = typename std::conditional<MIXED, float, double>::type;
   __shared__ PairLds<T> P;
   __shared__ double s_mass[4];
@@ -105,7 +109,8 @@ __global__ __launch_bounds__(kTile) void k_force(
   const int32_t tile_id = lb / TPP;
   const int32_t sub = lb % TPP;
   const Tile t = tiles[tile_id];
-  const double L = reps[t.rep].L;
+  const RepDesc& Rp = reps[t.rep];
+  const double L = Rp.L;
   const int32_t lane_p = threadIdx.x % TPP;
   const int32_t i = t.start + sub * (kTile / TPP) + threadIdx.x / TPP;
   const bool active = i < t.end;
@@ -115,8 +120,6 @@ __global__ __launch_bounds__(kTile) void k_force(
   T pe_i = 0, w_i = 0;
   int32_t ti = 0;
   if (active) {
-    const double4 p = pos[i];
-    ti = (int32_t)p.w;
     int32_t n = ncount[i];
     n = n < cap ? n : cap;
     const uint32_t* row = nbr + i;
@@ -129,49 +132,106 @@ __global__ __launch_bounds__(kTile) void k_force(
       const int32_t k = lane_p + u * TPP;
       e[u] = k < n ? row[(size_t)k * stride] : self;
     }
-    for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
-      double4 q[U];
+    if constexpr (MIXED) {
+      // 16-byte cell-relative records (see make_rec16)
+      const float4 pi = pos16[i];
+      const uint32_t wi = __float_as_uint(pi.w);
+      const int32_t cxi = (int32_t)(wi & 1023u), cyi = (int32_t)((wi >> 10) & 1023u),
+                    czi = (int32_t)((wi >> 20) & 1023u);
+      ti = (int32_t)(wi >> 30);
+      const float sf = (float)Rp.cside, df = (float)Rp.cdelta;
+      const int32_t nc = Rp.nc;
+      for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
+        float4 q[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) q[u] = pos[e[u] & kIdxMask];
-      uint32_t en[U];
+        for (int u = 0; u < U; ++u) q[u] = pos16[e[u] & kIdxMask];
+        uint32_t en[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int32_t k = k0 + (U + u) * TPP;
-        en[u] = k < n ? row[(size_t)k * stride] : self;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        double dx = p.x - q[u].x, dy = p.y - q[u].y, dz = p.z - q[u].z;
-        if (e[u] >> kIdxBits) {
-          // x_i - (x_j + s L)
-          dx -= (double)decode_shift(e[u], 26) * L;
-          dy -= (double)decode_shift(e[u], 28) * L;
-          dz -= (double)decode_shift(e[u], 30) * L;
+        for (int u = 0; u < U; ++u) {
+          const int32_t k = k0 + (U + u) * TPP;
+          en[u] = k < n ? row[(size_t)k * stride] : self;
         }
-        const int32_t ab = ti * 4 + (int32_t)q[u].w;
-        const T ddx = (T)dx, ddy = (T)dy, ddz = (T)dz;
-        const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-        if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
-          T rinv;
-          if constexpr (MIXED)
-            rinv = __builtin_amdgcn_rsqf(r2);
-          else
-            rinv = rsqrt_nr(r2);
-          const T r2inv = rinv * rinv;
-          const T sr2 = P.sig2[ab] * r2inv;
-          const T sr6 = sr2 * sr2 * sr2;
-          const T sr12 = sr6 * sr6;
-          const T fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
-          fx += fr * ddx;
-          fy += fr * ddy;
-          fz += fr * ddz;
-          pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
-                  (r2 * rinv - P.rc[ab]) * P.fs[ab];
-          w_i += fr * r2;
-        }
-      }
 #pragma unroll
-      for (int u = 0; u < U; ++u) e[u] = en[u];
+        for (int u = 0; u < U; ++u) {
+          const uint32_t wj = __float_as_uint(q[u].w);
+          int32_t mx = cxi - (int32_t)(wj & 1023u), my = cyi - (int32_t)((wj >> 10) & 1023u),
+                  mz = czi - (int32_t)((wj >> 20) & 1023u);
+          float ddx = pi.x - q[u].x, ddy = pi.y - q[u].y, ddz = pi.z - q[u].z;
+          if (e[u] >> kIdxBits) {
+            const int32_t sx = decode_shift(e[u], 26), sy = decode_shift(e[u], 28),
+                          sz = decode_shift(e[u], 30);
+            mx -= sx * nc;
+            my -= sy * nc;
+            mz -= sz * nc;
+            ddx -= (float)sx * df;
+            ddy -= (float)sy * df;
+            ddz -= (float)sz * df;
+          }
+          ddx += (float)mx * sf;
+          ddy += (float)my * sf;
+          ddz += (float)mz * sf;
+          const int32_t ab = ti * 4 + (int32_t)(wj >> 30);
+          const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float r2inv = rinv * rinv;
+            const float sr2 = P.sig2[ab] * r2inv;
+            const float sr6 = sr2 * sr2 * sr2;
+            const float sr12 = sr6 * sr6;
+            const float fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
+            fx += fr * ddx;
+            fy += fr * ddy;
+            fz += fr * ddz;
+            pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
+                    (r2 * rinv - P.rc[ab]) * P.fs[ab];
+            w_i += fr * r2;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) e[u] = en[u];
+      }
+    } else {
+      const double4 p = pos[i];
+      ti = (int32_t)p.w;
+      for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
+        double4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = pos[e[u] & kIdxMask];
+        uint32_t en[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t k = k0 + (U + u) * TPP;
+          en[u] = k < n ? row[(size_t)k * stride] : self;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          double dx = p.x - q[u].x, dy = p.y - q[u].y, dz = p.z - q[u].z;
+          if (e[u] >> kIdxBits) {
+            // x_i - (x_j + s L)
+            dx -= (double)decode_shift(e[u], 26) * L;
+            dy -= (double)decode_shift(e[u], 28) * L;
+            dz -= (double)decode_shift(e[u], 30) * L;
+          }
+          const int32_t ab = ti * 4 + (int32_t)q[u].w;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
+            const double rinv = rsqrt_nr(r2);
+            const double r2inv = rinv * rinv;
+            const double sr2 = P.sig2[ab] * r2inv;
+            const double sr6 = sr2 * sr2 * sr2;
+            const double sr12 = sr6 * sr6;
+            const double fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
+            fx += fr * dx;
+            fy += fr * dy;
+            fz += fr * dz;
+            pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
+                    (r2 * rinv - P.rc[ab]) * P.fs[ab];
+            w_i += fr * r2;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) e[u] = en[u];
+      }
     }
   }
   if constexpr (TPP > 1) {
@@ -216,13 +276,13 @@ __global__ __launch_bounds__(kTile) void k_force(
 
 template <bool MIXED, int MODE>
 void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const Tile* tiles,
-              const RepDesc* reps, const PairTab* tab, const double4* pos, double* vel,
-              void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride, int32_t cap,
-              double dt, double* part, DevState* st) {
-#define KF(TPP, U)                                                                            \
-  k_force<MIXED, MODE, TPP, U><<<ntiles * TPP, kTile, 0, s>>>(tiles, reps, tab, pos, vel, frc, \
-                                                              nbr, ncount, stride, cap, dt,    \
-                                                              part, st)
+              const RepDesc* reps, const PairTab* tab, const double4* pos, const float4* pos16,
+              double* vel, void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
+              int32_t cap, double dt, double* part, DevState* st) {
+#define KF(TPP, U)                                                                       \
+  k_force<MIXED, MODE, TPP, U><<<ntiles * TPP, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, \
+                                                              vel, frc, nbr, ncount, stride, \
+                                                              cap, dt, part, st)
   const int key = tpp * 16 + unroll;
   switch (key) {
     case 1 * 16 + 1: KF(1, 1); break;
@@ -245,12 +305,12 @@ void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const 
 // per particle, tile t owns logical blocks [t*tpp, (t+1)*tpp).
 void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
                   int32_t ntiles, const Tile* tiles, const RepDesc* reps, const PairTab* tab,
-                  const double4* pos, double* vel, void* frc, const uint32_t* nbr,
-                  const int32_t* ncount, int32_t stride, int32_t cap, double dt, double* part,
-                  DevState* st) {
-#define LT(M, MO)                                                                              \
-  launch_t<M, MO>(s, tpp, unroll, ntiles, tiles, reps, tab, pos, vel, frc, nbr, ncount, stride, \
-                  cap, dt, part, st)
+                  const double4* pos, const float4* pos16, double* vel, void* frc,
+                  const uint32_t* nbr, const int32_t* ncount, int32_t stride, int32_t cap,
+                  double dt, double* part, DevState* st) {
+#define LT(M, MO)                                                                        \
+  launch_t<M, MO>(s, tpp, unroll, ntiles, tiles, reps, tab, pos, pos16, vel, frc, nbr,    \
+                  ncount, stride, cap, dt, part, st)
   if (mixed) {
     if (mode) LT(true, 1); else LT(true, 0);
   } else {

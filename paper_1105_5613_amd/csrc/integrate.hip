@@ -20,8 +20,9 @@ namespace {
 template <typename FT, bool THERMO>
 __global__ __launch_bounds__(kTile) void k_kick_drift(
     const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
-    const PairTab* __restrict__ tab, double4* __restrict__ pos, double* __restrict__ vel,
-    const FT* __restrict__ frc, const double* __restrict__ xref, int32_t stride, double dt,
+    const PairTab* __restrict__ tab, double4* __restrict__ pos, float4* __restrict__ pos16,
+    double* __restrict__ vel, const FT* __restrict__ frc, const double* __restrict__ xref,
+    int32_t stride, double dt,
     const double* __restrict__ lam, int32_t* __restrict__ rebuild,
     unsigned long long* __restrict__ maxd2, DevState* st) {
   __shared__ double s_im[4];
@@ -48,6 +49,7 @@ __global__ __launch_bounds__(kTile) void k_kick_drift(
     p.y += dt * v1;
     p.z += dt * v2;
     pos[i] = p;
+    if (pos16) pos16[i] = make_rec16(p.x, p.y, p.z, __float_as_uint(pos16[i].w), reps[t.rep].cside);
     vel[i] = v0;
     vel[stride + i] = v1;
     vel[2 * (size_t)stride + i] = v2;
@@ -83,24 +85,25 @@ __device__ inline void neumaier(double& s, double& c, double x) {
 
 // One block per replica: compensated sums of the per-block partials in a
 // fixed order (deterministic), then observables and the thermostat factor.
-__global__ __launch_bounds__(256) void k_reduce(const RepDesc* __restrict__ reps,
-                                                const double* __restrict__ part,
-                                                int32_t step, ThermoArgs ta,
-                                                int64_t* __restrict__ kcall,
-                                                double* __restrict__ lam,
-                                                int32_t* __restrict__ rebuild,
-                                                unsigned long long* __restrict__ maxd2,
-                                                md_obs* __restrict__ obs, DevState* st) {
-  __shared__ double red[3][256];
+constexpr int kRedThreads = 1024;
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restrict__ reps,
+                                                        const double* __restrict__ part,
+                                                        int32_t step, ThermoArgs ta,
+                                                        int64_t* __restrict__ kcall,
+                                                        double* __restrict__ lam,
+                                                        int32_t* __restrict__ rebuild,
+                                                        unsigned long long* __restrict__ maxd2,
+                                                        md_obs* __restrict__ obs, DevState* st) {
+  __shared__ double red[3][kRedThreads];
   const int32_t r = blockIdx.x;
   const RepDesc R = reps[r];
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
   const int32_t b0 = R.fb0, b1 = R.fb1;
-  for (int32_t b = b0 + threadIdx.x; b < b1; b += 256)
+  for (int32_t b = b0 + threadIdx.x; b < b1; b += kRedThreads)
     for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
   for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
   __syncthreads();
-  for (int h = 128; h >= 1; h >>= 1) {
+  for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
     if (threadIdx.x < h)
       for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
     __syncthreads();
@@ -194,12 +197,13 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t ntiles,
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab, double4* pos,
-                       double* vel, const void* frc, const double* xref, int32_t stride,
-                       double dt, const double* lam, int32_t* rebuild, unsigned long long* maxd2,
-                       DevState* st) {
-#define KD(FT, TH)                                                                          \
-  k_kick_drift<FT, TH><<<ntiles, kTile, 0, s>>>(tiles, reps, tab, pos, vel, (const FT*)frc, \
-                                                xref, stride, dt, lam, rebuild, maxd2, st)
+                       float4* pos16, double* vel, const void* frc, const double* xref,
+                       int32_t stride, double dt, const double* lam, int32_t* rebuild,
+                       unsigned long long* maxd2, DevState* st) {
+#define KD(FT, TH)                                                                         \
+  k_kick_drift<FT, TH><<<ntiles, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, vel,         \
+                                                (const FT*)frc, xref, stride, dt, lam,     \
+                                                rebuild, maxd2, st)
   if (mixed) {
     if (thermo) KD(float, true); else KD(float, false);
   } else {
@@ -211,7 +215,8 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
                    int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
                    int32_t* rebuild, unsigned long long* maxd2, md_obs* obs, DevState* st) {
-  k_reduce<<<nrep, 256, 0, s>>>(reps, part, step, ta, kcall, lam, rebuild, maxd2, obs, st);
+  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, step, ta, kcall, lam, rebuild, maxd2, obs,
+                                        st);
 }
 
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, unsigned long long* maxd2,

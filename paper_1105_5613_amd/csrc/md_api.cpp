@@ -36,6 +36,7 @@ struct md_ctx_s {
   int32_t *cell_rep = nullptr, *counts = nullptr, *cell_start = nullptr, *bsum = nullptr;
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp_src = nullptr;
   double4 *pos = nullptr, *pos_tmp = nullptr;
+  float4* pos16 = nullptr;  // mixed form, gather path: cell-relative FP32 records
   double *vel = nullptr, *vel_tmp = nullptr, *xref = nullptr;
   void* frc = nullptr;
   int32_t *id = nullptr, *id_tmp = nullptr, *img = nullptr;
@@ -192,7 +193,7 @@ void run_chain(md_ctx c) {
     launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->p.ntypes, c->cell_start,
                  c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
                  c->xref, c->nbr, c->ncount, c->st, c->ncells, c->cell_rep, c->any_single,
-                 c->any_multi);
+                 c->any_multi, c->pos16);
 }
 
 void launch_forces(md_ctx c, int32_t mode) {
@@ -202,8 +203,8 @@ void launch_forces(md_ctx c, int32_t mode) {
                         c->nsplit, c->stride, c->cap, c->lcap_f, c->p.dt, c->part, c->st);
   else
     launch_force(c->stream, c->mixed, mode, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps,
-                 c->tab, c->pos, c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt,
-                 c->part, c->st);
+                 c->tab, c->pos, c->pos16, c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap,
+                 c->p.dt, c->part, c->st);
 }
 
 md_status grow_capacity(md_ctx c) {
@@ -305,6 +306,8 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     d.half_skin2 = (0.5 * p->skin) * (0.5 * p->skin);
     d.dof = 3.0 * (double)n[r] - 3.0;
     d.volume = L[r] * L[r] * L[r];
+    d.cside = (double)(float)(L[r] / nc);
+    d.cdelta = L[r] - (double)nc * d.cside;
     d.off = off;
     d.n = (int32_t)n[r];
     d.coff = coff;
@@ -344,6 +347,13 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     return fail(nullptr, MD_EINVAL, "the staged path needs >= 3 cells per box side");
   }
   c->staged = p->path == MD_PATH_STAGED;
+  if (c->mixed && !c->staged)
+    for (const RepDesc& d : c->reps_h)
+      if (d.nc > 1023) {
+        delete c;
+        return fail(nullptr, MD_EINVAL,
+                    "mixed precision on the gather path supports up to 1023 cells per side");
+      }
   c->bt = p->tile_threads ? p->tile_threads : 256;
   int32_t lds_max = 65536;
   {
@@ -473,6 +483,7 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     ALLOC(f, 3 * S);
     c->frc = f;
   }
+  if (c->mixed && !c->staged) ALLOC(c->pos16, S);
   ALLOC(c->id, N);
   ALLOC(c->id_tmp, N);
   ALLOC(c->img, 3 * N);
@@ -634,8 +645,9 @@ md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
   hipStream_t s = c->stream;
   launch_begin_call(s, c->nrep, c->kcall, c->lam);
   for (int32_t k = 0; k < nsteps; ++k) {
-    launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->vel,
-                      c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->maxd2, c->st);
+    launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16,
+                      c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->maxd2,
+                      c->st);
     run_chain(c);
     const bool timed = c->prof_every > 0 && (k + 1) % c->prof_every == 0;
     if (timed) {

@@ -53,7 +53,26 @@ struct RepDesc {       // per-replica geometry, device resident
   int32_t coff, nc;    // first cell, cells per side
   int32_t tile0, tile1;// tiles [tile0, tile1)
   int32_t fb0, fb1;    // force-kernel partial blocks [fb0, fb1) of this replica
+  double cside;        // cell side rounded to FP32 (exact in both precisions)
+  double cdelta;       // L - nc * cside (periodic-image correction of the mixed form)
 };
+
+// Mixed form gather record of a particle (16 B): FP32 offsets from the centre
+// of the cell it was binned into at the last list build, (c + 1/2) * cside,
+// and a word holding the cell coordinates (10 bits each) and the species
+// (bits 30-31).  The displacement of a listed pair is then, in FP32,
+//   (off_i - off_j) + (c_i - c_j - s nc) * cside - s * cdelta,
+// with s the periodic image of the entry.
+__device__ inline uint32_t pack_cell(int32_t cx, int32_t cy, int32_t cz, int32_t t) {
+  return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20) | ((uint32_t)t << 30);
+}
+__device__ inline float4 make_rec16(double x, double y, double z, uint32_t w, double cside) {
+  const int32_t cx = (int32_t)(w & 1023u), cy = (int32_t)((w >> 10) & 1023u),
+                cz = (int32_t)((w >> 20) & 1023u);
+  return make_float4((float)(x - ((double)cx + 0.5) * cside),
+                     (float)(y - ((double)cy + 0.5) * cside),
+                     (float)(z - ((double)cz + 0.5) * cside), __uint_as_float(w));
+}
 
 // Per species pair ab = a * 4 + b.  The pair function Eq. (3) is written as
 //   V*(r) = c12 (s/r)^12 + c6 (s/r)^6 - vc - (r - rc) fs
@@ -121,22 +140,23 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                   double4* pos, double* vel, int32_t* id, double* xref,
                   uint32_t* nbr, int32_t* ncount, DevState* st, int32_t ncells,
-                  const int32_t* cell_rep, int32_t any_single, int32_t any_multi);
+                  const int32_t* cell_rep, int32_t any_single, int32_t any_multi,
+                  float4* pos16);
 // force.hip
 // mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
 // half kick v += dt/2 F/m before KE.
 // unroll: list slots gathered per pipelined chunk (1, 2, 4 or 8).
 void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
                   int32_t ntiles, const Tile* tiles, const RepDesc* reps, const PairTab* tab,
-                  const double4* pos, double* vel, void* frc, const uint32_t* nbr,
-                  const int32_t* ncount, int32_t stride, int32_t cap, double dt,
-                  double* part, DevState* st);
+                  const double4* pos, const float4* pos16, double* vel, void* frc,
+                  const uint32_t* nbr, const int32_t* ncount, int32_t stride, int32_t cap,
+                  double dt, double* part, DevState* st);
 // integrate.hip
 void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t ntiles,
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab,
-                       double4* pos, double* vel, const void* frc, const double* xref,
-                       int32_t stride, double dt, const double* lam, int32_t* rebuild,
-                       unsigned long long* maxd2, DevState* st);
+                       double4* pos, float4* pos16, double* vel, const void* frc,
+                       const double* xref, int32_t stride, double dt, const double* lam,
+                       int32_t* rebuild, unsigned long long* maxd2, DevState* st);
 struct ThermoArgs {
   const double* T0;    // [nrep]
   const double* T1;    // [nrep]

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
     const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
     const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
     int32_t* __restrict__ id, double* __restrict__ xref, uint32_t* __restrict__ nbr,
-    int32_t* __restrict__ ncount, DevState* st, int32_t skip_multi) {
+    int32_t* __restrict__ ncount, DevState* st, int32_t skip_multi, float4* __restrict__ pos16) {
   __shared__ double s_thr[16];
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
@@ -157,6 +157,11 @@ __global__ __launch_bounds__(kTile) void k_nlist(
   ncount[i] = cnt;
   if (cnt > cap) atomicOr(&st->err, kErrOverflow);
   // the new cell order becomes the live state; the list is built on it
+  if (pos16) {
+    const uint32_t wc = pack_cell(cell_coord(p.x, R.inv_cell, R.nc), cell_coord(p.y, R.inv_cell, R.nc),
+                                  cell_coord(p.z, R.inv_cell, R.nc), ti);
+    pos16[i] = make_rec16(p.x, p.y, p.z, wc, R.cside);
+  }
   pos[i] = p;
   xref[i] = p.x;
   xref[stride + i] = p.y;
@@ -200,7 +205,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
     const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
     const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
     int32_t* __restrict__ id, double* __restrict__ xref, uint32_t* __restrict__ nbr,
-    int32_t* __restrict__ ncount, DevState* st) {
+    int32_t* __restrict__ ncount, DevState* st, float4* __restrict__ pos16) {
   __shared__ double s_thr[16];
   __shared__ int32_t s_pre[4][28];    // first packed candidate of piece p
   __shared__ int32_t s_k0[4][27];     // first sorted index of piece p
@@ -316,6 +321,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   for (int32_t h = lane; h < nh; h += 64) {
     const int32_t i = h0 + h;
     const double4 p4 = pos_tmp[i];
+    if (pos16) pos16[i] = make_rec16(p4.x, p4.y, p4.z, pack_cell(qx, qy, qz, (int32_t)p4.w), R.cside);
     pos[i] = p4;
     xref[i] = p4.x;
     xref[stride + i] = p4.y;
@@ -335,15 +341,16 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                   double4* pos, double* vel, int32_t* id, double* xref, uint32_t* nbr,
                   int32_t* ncount, DevState* st, int32_t ncells, const int32_t* cell_rep,
-                  int32_t any_single, int32_t any_multi) {
+                  int32_t any_single, int32_t any_multi, float4* pos16) {
   if (any_multi)
     k_nlist_cells<<<(ncells + 3) / 4, 256, 0, s>>>(ncells, cell_rep, reps, rebuild, tab,
                                                    cell_start, stride, cap, pos_tmp, vel_tmp,
-                                                   id_tmp, pos, vel, id, xref, nbr, ncount, st);
+                                                   id_tmp, pos, vel, id, xref, nbr, ncount, st,
+                                                   pos16);
   if (any_single)
     k_nlist<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, tab, ntypes, cell_start, stride, cap,
                                      pos_tmp, vel_tmp, id_tmp, pos, vel, id, xref, nbr, ncount,
-                                     st, 1);
+                                     st, 1, pos16);
 }
 
 }  // namespace mdk
