@@ -5,18 +5,27 @@ One step = one velocity-Verlet step of the whole path (kick + drift + skin
 check, cell binning/sort and neighbour search when due, pair forces with the
 second half kick, energy/virial reductions) over the whole system.
 
-Workload (default): 1,048,576-particle binary Lennard-Jones mixture (80:20,
+Headline workload: 1,048,576-particle binary Lennard-Jones mixture (80:20,
 eps/sigma tensors of the paper's mixture, rc = 2.5 sigma_ab shifted force),
 number density 1.2, FCC + 0.05 sigma jitter, Maxwell velocities at T = 2.0,
 NVE, dt = 0.005, skin 0.3 sigma.  Inputs are seeded synthetic arrays resident
-in HBM before the timed region.  `value` is the plain FP64 path; the FP32-force
-mixed form and the batched-replica form are reported beside it.
+in HBM before the timed region.  `value` is the plain FP64 path; the
+FP32-force mixed form and the batched-replica form (256 boxes of 1,000 to
+65,536 particles at T in [0.4, 2.0] with the velocity-rescale thermostat) are
+reported beside it.
 
 Prints one JSON line on stdout; progress goes to stderr.
+
+Other modes (used to make the committed profiles/ summaries):
+  --calibrate-copy          a plain 1 GiB device copy (counter calibration)
+  --counters-summary DIRS   turn rocprofv3 --pmc outputs into
+                            profiles/force_counters.json
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
@@ -26,6 +35,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "particle-steps/sec on 1 MI355X + % HBM roofline; mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+FORCE_SRC = os.path.join(ROOT, "paper_1105_5613_amd", "csrc", "force.hip")
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "force_counters.json")
+COPY_BYTES = 1 << 30
 
 
 def log(*a):
@@ -42,26 +54,32 @@ def force_bytes_per_particle(nbar: float, mixed: bool) -> float:
     return 4 + 4 * nbar + 24 + 4 + (12 if mixed else 24) + 48
 
 
-def counters_traffic(kernel_src: str, key: str):
-    """HBM bytes per force launch from committed rocprofv3 counter runs, or None
-    when the force kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "force_counters.json")
-    if not os.path.exists(path):
+def src_sha() -> str:
+    return hashlib.sha256(open(FORCE_SRC, "rb").read()).hexdigest()
+
+
+def counters_traffic(key: str):
+    """HBM bytes per force launch from the committed rocprofv3 counter runs, or
+    None when the force kernel source changed since the counters were taken."""
+    if not os.path.exists(COUNTERS_JSON):
         return None
-    with open(path) as f:
+    with open(COUNTERS_JSON) as f:
         d = json.load(f)
-    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    ent = d.get(key)
-    if not ent or d.get("force_src_sha256") != sha:
+    ent = d.get("forms", {}).get(key)
+    if not ent or d.get("force_src_sha256") != src_sha():
         return None
     return ent["fetch_kib"] * 1024 * d["copy_factor_fetch"] + \
         ent["write_kib"] * 1024 * d["copy_factor_write"]
 
 
-def run_form(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int):
-    from paper_1105_5613_amd import System, make_params
+def mixture():
     import initconf
-    eps, sig, rc, mass = initconf.mixture_tables()
+    return initconf.mixture_tables()
+
+
+def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int):
+    from paper_1105_5613_amd import System, make_params
+    eps, sig, rc, mass = mixture()
     p = make_params(eps, sig, rc, mass, skin=0.3, dt=0.005, precision=precision)
     n = inputs["n"]
     sysm = System(p, [n], [inputs["L"]])
@@ -84,10 +102,60 @@ def run_form(torch, precision: int, inputs, steps: int, warmup: int, prof_every:
             "rebuilds": obs["n_rebuild"], "steps_total": obs["step"]}
 
 
-def cpu_baseline(inputs, nsteps: int):
+def replica_inputs(nrep: int):
     import initconf
+    sizes = initconf.replica_sizes(nrep, 1000, 65536, seed=4)
+    temps = initconf.replica_temperatures(nrep, 0.4, 2.0, seed=4)
+    systems = initconf.batched_systems(sizes, temps, seed=4)
+    return systems, temps
+
+
+def run_batched(torch, precision: int, systems, temps, steps: int, warmup: int):
+    import initconf
+    from paper_1105_5613_amd import System, make_params
+    eps, sig, rc, mass = mixture()
+    x, v, t, n, L = initconf.concat_replicas(systems)
+    p = make_params(eps, sig, rc, mass, skin=0.3, dt=0.005, precision=precision)
+    sysm = System(p, n, L)
+    sysm.set_state(x, v, t)
+    sysm.step(warmup, T0=temps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysm.step(steps, T0=temps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    obs = sysm.observables()
+    sysm.close()
+    terr = max(abs(o["T"] - tt) / tt for o, tt in zip(obs, temps))
+    return {"rate": sum(n) * steps / wall, "ms_per_step": 1e3 * wall / steps,
+            "particles": sum(n), "max_rel_T_error": terr}
+
+
+def run_one_at_a_time(torch, systems, temps, steps: int):
+    """The same replicas, each its own context, plain FP64, run one after another."""
+    from paper_1105_5613_amd import System, make_params
+    eps, sig, rc, mass = mixture()
+    p = make_params(eps, sig, rc, mass, skin=0.3, dt=0.005, precision=0)
+    ctxs = []
+    for s, tt in zip(systems, temps):
+        c = System(p, [s["n"]], [s["L"]])
+        c.set_state(s["x"], s["v"], s["type"])
+        c.step(5, T0=[tt])
+        ctxs.append((c, tt))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, tt in ctxs:
+        c.step(steps, T0=[tt])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for c, _ in ctxs:
+        c.close()
+    return {"rate": sum(s["n"] for s in systems) * steps / wall, "steps": steps}
+
+
+def cpu_baseline(inputs, nsteps: int):
     import oracle
-    eps, sig, rc, mass = initconf.mixture_tables()
+    eps, sig, rc, mass = mixture()
     p = oracle.make_params(eps, sig, rc, mass, skin=0.3)
     sim = oracle.Sim(p, inputs["n"], inputs["L"], 0.005)
     sim.set_state(inputs["x"], inputs["v"], inputs["type"])
@@ -103,75 +171,165 @@ def cpu_baseline(inputs, nsteps: int):
                       f"oracle, OpenMP over particles, {wall:.1f} s"}
 
 
+def calibrate_copy(torch):
+    """A plain device-to-device copy of COPY_BYTES (counter calibration)."""
+    a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {COPY_BYTES} bytes 3 times")
+
+
+def _counter_rows(d, name_part):
+    out = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if name_part in r["Kernel_Name"]:
+                out.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(
+                    float(r["Counter_Value"]))
+    return out
+
+
+def counters_summary(args):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the in-step force kernels,
+    scaled by what the same counters read for the plain copy."""
+    def mean_for(d, kern, counter, keyword):
+        rows = _counter_rows(d, kern)
+        vals = [v for (k, c), vs in rows.items() if c == counter and keyword in k for v in vs]
+        return sum(vals) / len(vals), len(vals)
+
+    cf, _ = mean_for(args.copy_fetch_dir, "", "FETCH_SIZE", "copy")
+    cw, _ = mean_for(args.copy_write_dir, "", "WRITE_SIZE", "copy")
+    copy_kib = COPY_BYTES / 1024
+    out = {"force_src_sha256": src_sha(),
+           "copy_bytes": COPY_BYTES, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "copy_factor_fetch": copy_kib / cf, "copy_factor_write": copy_kib / cw,
+           "forms": {}, "commands": args.commands}
+    for form, key in (("fp64", "k_force<false, 1"), ("mixed", "k_force<true, 1")):
+        try:
+            f, nf = mean_for(args.fetch_dir, "k_force", "FETCH_SIZE", key)
+            w, nw = mean_for(args.write_dir, "k_force", "WRITE_SIZE", key)
+        except ZeroDivisionError:
+            continue
+        out["forms"][form] = {"fetch_kib": f, "write_kib": w, "dispatches": nf}
+    os.makedirs(os.path.dirname(COUNTERS_JSON), exist_ok=True)
+    with open(COUNTERS_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--forms", default="fp64,mixed,batched")
     ap.add_argument("--profile-every", type=int, default=4,
                     help="bracket the force launch of every k-th timed step with hipEvents")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1048576)
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--serial-steps", type=int, default=50)
+    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--counters-summary", action="store_true")
+    ap.add_argument("--fetch-dir")
+    ap.add_argument("--write-dir")
+    ap.add_argument("--copy-fetch-dir")
+    ap.add_argument("--copy-write-dir")
+    ap.add_argument("--commands", default="")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     sys.path.insert(0, ROOT)
+    if args.counters_summary:
+        counters_summary(args)
+        return
     import torch
-    import initconf
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    log(f"generating inputs n={args.n}")
-    inputs = initconf.fcc_system(args.n, seed=2, temperature=2.0)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
+    import initconf
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    n = args.n
+    log(f"generating inputs n={n}")
+    inputs = initconf.fcc_system(n, seed=2, temperature=2.0)
     res = {}
     for f in forms:
         if f not in ("fp64", "mixed"):
             continue
         log(f"timing form {f}: {args.steps} steps after {args.warmup} warmup")
-        res[f] = run_form(torch, 1 if f == "mixed" else 0, inputs, args.steps, args.warmup,
-                          args.profile_every)
+        res[f] = run_single(torch, 1 if f == "mixed" else 0, inputs, args.steps, args.warmup,
+                            args.profile_every)
         log(f"  {f}: {res[f]['rate']:.4e} particle-steps/s, {res[f]['ms_per_step']:.4f} ms/step, "
             f"force {res[f]['force_ms_avg']:.4f} ms, nbar {res[f]['nbar']:.2f}, "
             f"rebuilds {res[f]['rebuilds']}")
-    head = res.get("fp64") or next(iter(res.values()))
-    head_mixed = "fp64" not in res
-    n = args.n
-    bpp = force_bytes_per_particle(head["nbar"], head_mixed)
-    achieved = n * bpp / (head["force_ms_avg"] * 1e-3) / 1e9
-    src = os.path.join(ROOT, "paper_1105_5613_amd", "csrc", "force.hip")
-    traffic = counters_traffic(src, "mixed" if head_mixed else "fp64")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if traffic is None else round(traffic),
-            "kernel": "k_force (pair forces + fused second half kick)",
-            "algorithmic_bytes_per_launch": round(n * bpp),
-            "force_ms_avg": round(head["force_ms_avg"], 5)}
     forms_out = {}
     for f, r in res.items():
         b = force_bytes_per_particle(r["nbar"], f == "mixed")
+        tr = counters_traffic(f)
         forms_out[f] = {"value": round(r["rate"], 1), "ms_per_step": round(r["ms_per_step"], 5),
                         "force_ms_avg": round(r["force_ms_avg"], 5),
-                        "force_frac_hbm": round(n * b / (r["force_ms_avg"] * 1e-3) / 1e9
+                        "force_achieved_gbs": round(n * b / (max(r["force_ms_avg"], 1e-12) * 1e-3) / 1e9, 1),
+                        "force_frac_hbm": round(n * b / (max(r["force_ms_avg"], 1e-12) * 1e-3) / 1e9
                                                 / HBM_PEAK_GBS, 4),
+                        "force_traffic_bytes": None if tr is None else round(tr),
                         "mean_list_length": round(r["nbar"], 3), "rebuilds": r["rebuilds"]}
     if "fp64" in res and "mixed" in res:
         forms_out["speedup_mixed_vs_fp64"] = round(res["mixed"]["rate"] / res["fp64"]["rate"], 4)
+    if "batched" in forms:
+        log(f"timing batched replicas: {args.replicas} boxes, {args.batched_steps} steps")
+        systems, temps = replica_inputs(args.replicas)
+        bf = run_batched(torch, 0, systems, temps, args.batched_steps, 20)
+        bm = run_batched(torch, 1, systems, temps, args.batched_steps, 20)
+        log(f"  batched fp64 {bf['rate']:.4e}, mixed {bm['rate']:.4e} particle-steps/s "
+            f"({bf['particles']} particles)")
+        log(f"timing the same replicas one at a time: {args.serial_steps} steps each")
+        ser = run_one_at_a_time(torch, systems, temps, args.serial_steps)
+        log(f"  one at a time fp64 {ser['rate']:.4e} particle-steps/s")
+        forms_out["batched"] = {
+            "workload": f"replicas{args.replicas}: sizes log-uniform 1000..65536 "
+                        f"({bf['particles']} particles), T0 in [0.4, 2.0], velocity rescale "
+                        "every step, dt 0.005, skin 0.3",
+            "value_fp64": round(bf["rate"], 1), "value_mixed": round(bm["rate"], 1),
+            "ms_per_step_fp64": round(bf["ms_per_step"], 5),
+            "one_at_a_time_fp64": round(ser["rate"], 1),
+            "speedup_batched_vs_one_at_a_time_fp64": round(bf["rate"] / ser["rate"], 3),
+            "speedup_batched_mixed_vs_one_at_a_time_fp64": round(bm["rate"] / ser["rate"], 3),
+            "max_rel_T_error": bf["max_rel_T_error"]}
+    head = res.get("fp64") or res.get("mixed")
+    head_mixed = "fp64" not in res
+    roof = None
+    if head is not None:
+        bpp = force_bytes_per_particle(head["nbar"], head_mixed)
+        achieved = n * bpp / (max(head["force_ms_avg"], 1e-12) * 1e-3) / 1e9
+        traffic = counters_traffic("mixed" if head_mixed else "fp64")
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "kernel": "k_force (pair forces + fused second half kick)",
+                "algorithmic_bytes_per_launch": round(n * bpp),
+                "force_ms_avg": round(head["force_ms_avg"], 5)}
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and head is not None:
         log(f"timing the CPU oracle: {args.cpu_steps} steps")
         cpu = cpu_baseline(inputs, args.cpu_steps)
         log(f"  oracle: {cpu['value']:.4e} particle-steps/s on {cpu['cores']} threads")
     out = {
-        "metric": METRIC, "value": round(head["rate"], 1), "unit": "particle-steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(head["ms_per_step"], 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32-force/f64" if head_mixed else "f64",
-        "data": "synthetic",
+        "metric": METRIC, "value": None if head is None else round(head["rate"], 1),
+        "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None if head is None else round(head["ms_per_step"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-force/f64" if head_mixed else "f64", "data": "synthetic",
         "config": {"workload": f"lj{n}: {n}-particle binary Lennard-Jones mixture 80:20, rho 1.2, "
                                "FCC+0.05 jitter, T=2.0 NVE, dt 0.005, rc 2.5 sigma_ab shifted "
                                "force, skin 0.3, full neighbour list",
