@@ -52,6 +52,11 @@ struct md_ctx_s {
   md_obs* log_dev = nullptr;
   int64_t log_cap = 0;
   std::vector<void*> owned;
+  // captured K-step graphs (md_params.graph_steps)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t gkey[10] = {0};
+  int32_t prof_epoch = 0;
   // force-kernel timing
   int32_t prof_every = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -175,8 +180,7 @@ md_status sync_and_check(md_ctx c) {
   return MD_OK;
 }
 
-void run_chain(md_ctx c) {
-  hipStream_t s = c->stream;
+void run_chain(md_ctx c, hipStream_t s) {
   launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
   launch_bin(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->pos, c->id, c->img, c->counts,
              c->cell_of, c->slot, c->st);
@@ -196,13 +200,13 @@ void run_chain(md_ctx c) {
                  c->any_multi, c->pos16);
 }
 
-void launch_forces(md_ctx c, int32_t mode) {
+void launch_forces(md_ctx c, int32_t mode, hipStream_t s) {
   if (c->staged)
-    launch_force_staged(c->stream, c->mixed, mode, c->bt, c->unroll, c->nrt, c->rtiles, c->reps,
+    launch_force_staged(s, c->mixed, mode, c->bt, c->unroll, c->nrt, c->rtiles, c->reps,
                         c->tab, c->cell_start, c->pos, c->vel, c->frc, c->nbr16, c->ncount,
                         c->nsplit, c->stride, c->cap, c->lcap_f, c->p.dt, c->part, c->st);
   else
-    launch_force(c->stream, c->mixed, mode, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps,
+    launch_force(s, c->mixed, mode, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps,
                  c->tab, c->pos, c->pos16, c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap,
                  c->p.dt, c->part, c->st);
 }
@@ -233,7 +237,7 @@ md_status grow_capacity(md_ctx c) {
 md_status build_all(md_ctx c) {
   for (int attempt = 0; attempt < 2; ++attempt) {
     launch_mark_rebuild(c->stream, c->nrep, c->rebuild, c->st);
-    run_chain(c);
+    run_chain(c, c->stream);
     launch_after_build(c->stream, c->nrep, c->rebuild, c->maxd2, c->obs, c->st);
     md_status rc = sync_and_check(c);
     if (rc == MD_OK) {
@@ -254,9 +258,77 @@ ThermoArgs no_thermo() {
 }
 
 void launch_forces0(md_ctx c) {
-  launch_forces(c, 0);
+  launch_forces(c, 0, c->stream);
   launch_reduce(c->stream, c->nrep, c->reps, c->part, 0, no_thermo(), c->kcall, c->lam,
                 c->rebuild, c->maxd2, c->obs, c->st);
+}
+
+
+// One velocity-Verlet step on stream s (also used while capturing a graph).
+md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t thermo, int32_t k) {
+  launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16,
+                    c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->maxd2,
+                    c->st);
+  run_chain(c, s);
+  const bool timed = c->prof_every > 0 && (k + 1) % c->prof_every == 0;
+  if (timed) {
+    if (c->ev_pool.size() < c->ev_used + 2) return fail(c, MD_EHIP, "event pool exhausted");
+    HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
+  }
+  launch_forces(c, 1, s);
+  if (timed) {
+    HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
+    c->ev_used += 2;
+  }
+  launch_reduce(s, c->nrep, c->reps, c->part, 1, ta, c->kcall, c->lam, c->rebuild, c->maxd2,
+                c->obs, c->st);
+  return MD_OK;
+}
+
+md_status reserve_events(md_ctx c, int32_t nsteps) {
+  if (c->prof_every <= 0) return MD_OK;
+  const size_t need = c->ev_used + 2 * (size_t)(nsteps / c->prof_every + 1);
+  while (c->ev_pool.size() < need) {
+    hipEvent_t e;
+    HIPCHECK(c, hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  return MD_OK;
+}
+
+void drop_graph(md_ctx c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+}
+
+// A graph of K steps, captured once per launch configuration and replayed:
+// every argument is fixed, the step number lives in device counters.
+md_status ensure_graph(md_ctx c, const ThermoArgs& ta, int32_t thermo, int32_t K) {
+  const int64_t key[10] = {K, thermo, ta.ramp, ta.log_every, ta.nlog, (int64_t)(intptr_t)ta.log,
+                           (int64_t)(intptr_t)c->nbr, (int64_t)(intptr_t)c->nbr16,
+                           c->prof_every, c->prof_epoch};
+  if (c->gexec && std::equal(key, key + 10, c->gkey)) return MD_OK;
+  drop_graph(c);
+  if (!c->cap_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  md_status rc = reserve_events(c, K);
+  if (rc) return rc;
+  HIPCHECK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+  for (int32_t k = 0; k < K && rc == MD_OK; ++k) rc = enqueue_step(c, c->cap_stream, ta, thermo, k);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(c, MD_EHIP, "graph capture failed");
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->gexec = nullptr;
+    return fail(c, MD_EHIP, "graph instantiation failed");
+  }
+  std::copy(key, key + 10, c->gkey);
+  return MD_OK;
 }
 
 }  // namespace
@@ -531,6 +603,8 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
 md_status md_destroy(md_ctx c) {
   if (!c) return MD_OK;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (void* p : c->owned) (void)hipFree(p);
   c->owned.clear();
@@ -644,27 +718,20 @@ md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
   }
   hipStream_t s = c->stream;
   launch_begin_call(s, c->nrep, c->kcall, c->lam);
-  for (int32_t k = 0; k < nsteps; ++k) {
-    launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16,
-                      c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->maxd2,
-                      c->st);
-    run_chain(c);
-    const bool timed = c->prof_every > 0 && (k + 1) % c->prof_every == 0;
-    if (timed) {
-      while (c->ev_pool.size() < c->ev_used + 2) {
-        hipEvent_t e;
-        HIPCHECK(c, hipEventCreate(&e));
-        c->ev_pool.push_back(e);
-      }
-      HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
-    }
-    launch_forces(c, 1);
-    if (timed) {
-      HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
-      c->ev_used += 2;
-    }
-    launch_reduce(s, c->nrep, c->reps, c->part, 1, ta, c->kcall, c->lam, c->rebuild, c->maxd2,
-                  c->obs, c->st);
+  int32_t k = 0;
+  const int32_t K = c->p.graph_steps;
+  if (K > 0 && nsteps >= K) {
+    md_status rc = ensure_graph(c, ta, thermo, K);
+    if (rc) return rc;
+    for (; k + K <= nsteps; k += K) HIPCHECK(c, hipGraphLaunch(c->gexec, s));
+  }
+  {
+    md_status rc = reserve_events(c, nsteps - k);
+    if (rc) return rc;
+  }
+  for (; k < nsteps; ++k) {
+    md_status rc = enqueue_step(c, s, ta, thermo, k);
+    if (rc) return rc;
   }
   if (thermo) launch_apply_lambda(s, c->ntiles, c->tiles, c->stride, c->vel, c->lam, c->nrep);
   HIPCHECK(c, hipGetLastError());
@@ -777,6 +844,7 @@ md_status md_profile(md_ctx c, int32_t every) {
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   c->prof_every = every;
   c->ev_used = 0;
+  c->prof_epoch += 1;  // captured graphs hold events of the previous setting
   return MD_OK;
 }
 

@@ -293,3 +293,42 @@ def test_deterministic(torch_cuda, path):
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
     assert np.array_equal(outs[0][2], outs[1][2])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_match_direct(torch_cuda, precision):
+    """K-step graphs replayed several times (two calls, ramp, log) give the
+    same bits as direct launches."""
+    say(f"case graph replays precision={precision}")
+    outs = []
+    for K in (0, 10):
+        sysm, s = make_system(torch_cuda, 4000, 5, precision=precision, graph_steps=K)
+        logs = [sysm.step(35, T0=1.5, T1=0.9, ramp=30, log_every=5)]
+        _ = sysm.get_state()  # eager work between the replays
+        logs.append(sysm.step(27, T0=0.9, T1=0.9, ramp=0, log_every=9))
+        x, v, img = sysm.get_state()
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), img.cpu().numpy(), logs))
+    (x0, v0, i0, l0), (x1, v1, i1, l1) = outs
+    assert np.array_equal(x0, x1) and np.array_equal(v0, v1) and np.array_equal(i0, i1)
+    for a, b in zip(l0, l1):
+        for k in ("E", "T", "pe", "virial", "step", "n_rebuild"):
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_checkpoint_resume(torch_cuda):
+    """200 steps straight vs 100 + get_state/set_state + 100."""
+    say("case checkpoint")
+    a, s = make_system(torch_cuda, 4000, 6)
+    a.step(200)
+    xa, va, ia = (t.cpu().numpy() for t in a.get_state())
+    b, _ = make_system(torch_cuda, 4000, 6)
+    b.step(100)
+    x, v, img = b.get_state()
+    c, _ = make_system(torch_cuda, 4000, 6)
+    c.set_state(x, v, s["type"])
+    c.step(100)
+    xc, vc, ic = (t.cpu().numpy() for t in c.get_state())
+    ua = xa + ia * s["L"]
+    uc = xc + (ic + img.cpu().numpy()) * s["L"]
+    assert np.max(np.abs(ua - uc)) < 1e-8
+    assert np.max(np.abs(va - vc)) < 1e-8
