@@ -85,6 +85,7 @@ def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_ever
     sysm = System(p, [n], [inputs["L"]])
     sysm.set_state(inputs["x"], inputs["v"], inputs["type"])
     sysm.step(warmup)
+    tuned = sysm.autotune(reps=3)
     sysm.profile(prof_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -99,7 +100,8 @@ def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_ever
     return {"wall_s": wall, "rate": n * steps / wall, "ms_per_step": 1e3 * wall / steps,
             "force_ms_avg": prof["force_ms"] / max(prof["force_launches"], 1),
             "force_launches_timed": prof["force_launches"], "nbar": nbar, "nmax": nmax,
-            "rebuilds": obs["n_rebuild"], "steps_total": obs["step"]}
+            "rebuilds": obs["n_rebuild"], "steps_total": obs["step"],
+            "tuned": {"tpp": tuned["tpp"], "unroll": tuned["unroll"]}}
 
 
 def replica_inputs(nrep: int):
@@ -110,15 +112,19 @@ def replica_inputs(nrep: int):
     return systems, temps
 
 
-def run_batched(torch, precision: int, systems, temps, steps: int, warmup: int):
+def run_batched(torch, precision: int, systems, temps, steps: int, warmup: int,
+                graph_steps: int):
     import initconf
     from paper_1105_5613_amd import System, make_params
     eps, sig, rc, mass = mixture()
     x, v, t, n, L = initconf.concat_replicas(systems)
-    p = make_params(eps, sig, rc, mass, skin=0.3, dt=0.005, precision=precision)
+    p = make_params(eps, sig, rc, mass, skin=0.3, dt=0.005, precision=precision,
+                    graph_steps=graph_steps)
     sysm = System(p, n, L)
     sysm.set_state(x, v, t)
     sysm.step(warmup, T0=temps)
+    tuned = sysm.autotune(reps=3)
+    sysm.step(graph_steps, T0=temps)  # captures the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sysm.step(steps, T0=temps)
@@ -128,7 +134,8 @@ def run_batched(torch, precision: int, systems, temps, steps: int, warmup: int):
     sysm.close()
     terr = max(abs(o["T"] - tt) / tt for o, tt in zip(obs, temps))
     return {"rate": sum(n) * steps / wall, "ms_per_step": 1e3 * wall / steps,
-            "particles": sum(n), "max_rel_T_error": terr}
+            "particles": sum(n), "max_rel_T_error": terr,
+            "tuned": {"tpp": tuned["tpp"], "unroll": tuned["unroll"]}}
 
 
 def run_one_at_a_time(torch, systems, temps, steps: int):
@@ -235,6 +242,8 @@ def main():
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--serial-steps", type=int, default=50)
+    ap.add_argument("--graph-steps", type=int, default=100,
+                    help="steps per captured hipGraph in the batched form (0: direct launches)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--counters-summary", action="store_true")
     ap.add_argument("--fetch-dir")
@@ -283,14 +292,15 @@ def main():
                         "force_frac_hbm": round(n * b / (max(r["force_ms_avg"], 1e-12) * 1e-3) / 1e9
                                                 / HBM_PEAK_GBS, 4),
                         "force_traffic_bytes": None if tr is None else round(tr),
-                        "mean_list_length": round(r["nbar"], 3), "rebuilds": r["rebuilds"]}
+                        "mean_list_length": round(r["nbar"], 3), "rebuilds": r["rebuilds"],
+                        "tuned": r["tuned"]}
     if "fp64" in res and "mixed" in res:
         forms_out["speedup_mixed_vs_fp64"] = round(res["mixed"]["rate"] / res["fp64"]["rate"], 4)
     if "batched" in forms:
         log(f"timing batched replicas: {args.replicas} boxes, {args.batched_steps} steps")
         systems, temps = replica_inputs(args.replicas)
-        bf = run_batched(torch, 0, systems, temps, args.batched_steps, 20)
-        bm = run_batched(torch, 1, systems, temps, args.batched_steps, 20)
+        bf = run_batched(torch, 0, systems, temps, args.batched_steps, 20, args.graph_steps)
+        bm = run_batched(torch, 1, systems, temps, args.batched_steps, 20, args.graph_steps)
         log(f"  batched fp64 {bf['rate']:.4e}, mixed {bm['rate']:.4e} particle-steps/s "
             f"({bf['particles']} particles)")
         log(f"timing the same replicas one at a time: {args.serial_steps} steps each")
@@ -299,7 +309,9 @@ def main():
         forms_out["batched"] = {
             "workload": f"replicas{args.replicas}: sizes log-uniform 1000..65536 "
                         f"({bf['particles']} particles), T0 in [0.4, 2.0], velocity rescale "
-                        "every step, dt 0.005, skin 0.3",
+                        f"every step, dt 0.005, skin 0.3, {args.graph_steps}-step hipGraph "
+                        "chunks, force variant autotuned",
+            "tuned_fp64": bf["tuned"], "tuned_mixed": bm["tuned"],
             "value_fp64": round(bf["rate"], 1), "value_mixed": round(bm["rate"], 1),
             "ms_per_step_fp64": round(bf["ms_per_step"], 5),
             "one_at_a_time_fp64": round(ser["rate"], 1),

@@ -197,6 +197,35 @@ typedef struct {
 md_status md_profile(md_ctx ctx, int32_t every);
 md_status md_profile_read(md_ctx ctx, md_prof* out);
 
+/* Autotuner: times every force-kernel variant of the context's path (lanes
+ * per particle x unroll on the gather path; unroll on the staged path) on
+ * the current state, `reps` launches each, with hipEvents on the context
+ * stream, keeps the fastest and recomputes forces and observables with it.
+ * Positions and velocities are not changed.  Synchronises. */
+typedef struct {
+  int32_t tpp, unroll;   /* chosen variant */
+  double force_ms;       /* its mean force-kernel time */
+  int32_t ntried;
+  int32_t tried_tpp[16], tried_unroll[16];
+  double tried_ms[16];
+} md_tune;
+md_status md_autotune(md_ctx ctx, int32_t reps, md_tune* out);
+
+/* Mean-squared displacement (glass section observables).  md_msd_reference
+ * stores the current unwrapped positions x + img L as the reference;
+ * md_msd returns, per replica (HOST [nrep]), the mean over its particles of
+ * |u - u_ref|^2.  md_msd fails with MD_ESTATE before a reference is set.
+ * Synchronises. */
+md_status md_msd_reference(md_ctx ctx);
+md_status md_msd(md_ctx ctx, double* out);
+
+/* Radial distribution function of replica rep (glass section):
+ * g[b] = 2V/N^2 * (number of pairs i < j with b dr <= r_ij < (b+1) dr) / shell
+ * volume of bin b, dr = rmax / nbins, minimum image, exact FP64 distances
+ * over all pairs.  rmax <= L/2, nbins <= 8192, replica size <= 262144.
+ * g HOST [nbins].  Synchronises. */
+md_status md_rdf(md_ctx ctx, int32_t rep, double rmax, int32_t nbins, double* g);
+
 /* Neighbour-list statistics of replica rep (rep = -1: all replicas) at the
  * last list build: mean and maximum entries per particle.  Synchronises. */
 md_status md_list_stats(md_ctx ctx, int32_t rep, double* mean, int32_t* max);

@@ -113,6 +113,11 @@ def fcc_system(n: int, *, rho: float = DENSITY, temperature: float = 2.0,
             "seed": seed, "temperature": temperature}
 
 
+def uniform_positions(n: int, L: float, seed: int = 1) -> np.ndarray:
+    """n positions drawn uniformly from the cube [0, L)^3 (an ideal gas)."""
+    return _rng(seed).random((n, 3)) * L
+
+
 def replica_sizes(nrep: int, nmin: int = 1000, nmax: int = 65536, seed: int = 4):
     """Log-uniform sizes N_r = round(exp(U[ln nmin, ln nmax]))."""
     rng = _rng(seed)

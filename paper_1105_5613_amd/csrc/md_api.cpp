@@ -49,6 +49,9 @@ struct md_ctx_s {
   int64_t* kcall = nullptr;
   double* lam = nullptr;
   double* therm = nullptr;  // T0 [nrep], T1 [nrep]
+  double* u0 = nullptr;     // MSD reference, original id order [N][3]
+  double* msd_part = nullptr;
+  double* msd_out = nullptr;
   md_obs* log_dev = nullptr;
   int64_t log_cap = 0;
   std::vector<void*> owned;
@@ -858,6 +861,125 @@ md_status md_profile_read(md_ctx c, md_prof* out) {
     float ms = 0.0f;
     HIPCHECK(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
     out->force_ms += ms;
+  }
+  return MD_OK;
+}
+
+md_status md_autotune(md_ctx c, int32_t reps, md_tune* out) {
+  if (!c) return MD_EINVAL;
+  if (!out || reps < 1) return fail(c, MD_EINVAL, "need out and reps >= 1");
+  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+  if (!c->built) {
+    md_status rc = build_all(c);
+    if (rc) return rc;
+  }
+  std::vector<std::pair<int32_t, int32_t>> cand;
+  if (c->staged)
+    cand = {{1, 2}, {1, 4}, {1, 8}};
+  else
+    cand = {{1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 1}, {4, 2}, {8, 1}};
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0));
+  HIPCHECK(c, hipEventCreate(&e1));
+  *out = md_tune{};
+  double best = 1e300;
+  int32_t btpp = c->tpp, bun = c->unroll;
+  for (auto& tu : cand) {
+    c->tpp = tu.first;
+    c->unroll = tu.second;
+    launch_forces(c, 0, c->stream);  // warm
+    HIPCHECK(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) launch_forces(c, 0, c->stream);
+    HIPCHECK(c, hipEventRecord(e1, c->stream));
+    HIPCHECK(c, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
+    const double avg = ms / reps;
+    if (out->ntried < 16) {
+      out->tried_tpp[out->ntried] = tu.first;
+      out->tried_unroll[out->ntried] = tu.second;
+      out->tried_ms[out->ntried] = avg;
+      out->ntried += 1;
+    }
+    if (avg < best) {
+      best = avg;
+      btpp = tu.first;
+      bun = tu.second;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tpp = btpp;
+  c->unroll = bun;
+  if (!c->staged) {
+    // partial-sum blocks per replica follow the lanes per particle
+    for (RepDesc& d : c->reps_h) {
+      d.fb0 = d.tile0 * c->tpp;
+      d.fb1 = d.tile1 * c->tpp;
+    }
+    HIPCHECK(c, hipMemcpyAsync(c->reps, c->reps_h.data(), sizeof(RepDesc) * c->nrep,
+                               hipMemcpyHostToDevice, c->stream));
+  }
+  drop_graph(c);
+  launch_forces0(c);
+  c->forces_valid = true;
+  out->tpp = btpp;
+  out->unroll = bun;
+  out->force_ms = best;
+  return sync_and_check(c);
+}
+
+md_status md_msd_reference(md_ctx c) {
+  if (!c) return MD_EINVAL;
+  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+  if (!c->u0) {
+    md_status rc = dalloc(c, &c->u0, 3 * (size_t)c->ntot);
+    if (!rc) rc = dalloc(c, &c->msd_part, (size_t)c->ntiles);
+    if (!rc) rc = dalloc(c, &c->msd_out, (size_t)c->nrep);
+    if (rc) return rc;
+  }
+  launch_msd_ref(c->stream, c->ntiles, c->tiles, c->reps, c->pos, c->id, c->img, c->u0);
+  return sync_and_check(c);
+}
+
+md_status md_msd(md_ctx c, double* out) {
+  if (!c) return MD_EINVAL;
+  if (!out) return fail(c, MD_EINVAL, "out is NULL");
+  if (!c->u0) return fail(c, MD_ESTATE, "no MSD reference set");
+  launch_msd(c->stream, c->ntiles, c->nrep, c->tiles, c->reps, c->pos, c->id, c->img, c->u0,
+             c->msd_part, c->msd_out);
+  md_status rc = sync_and_check(c);
+  if (rc) return rc;
+  HIPCHECK(c, hipMemcpy(out, c->msd_out, sizeof(double) * c->nrep, hipMemcpyDeviceToHost));
+  return MD_OK;
+}
+
+md_status md_rdf(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g) {
+  if (!c) return MD_EINVAL;
+  if (rep < 0 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
+  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+  const RepDesc& d = c->reps_h[rep];
+  if (!g || nbins < 1 || nbins > 8192 || !(rmax > 0.0) || rmax > 0.5 * d.L)
+    return fail(c, MD_EINVAL, "need g, 1 <= nbins <= 8192 and 0 < rmax <= L/2");
+  if (d.n > 262144) return fail(c, MD_EINVAL, "md_rdf supports replicas of up to 262144 particles");
+  unsigned long long* hist = nullptr;
+  md_status rc = dalloc(c, &hist, (size_t)nbins);
+  if (rc) return rc;
+  hipError_t e = hipMemsetAsync(hist, 0, sizeof(unsigned long long) * nbins, c->stream);
+  if (e == hipSuccess) launch_rdf(c->stream, c->pos, d.off, d.n, d.L, rmax, nbins, hist);
+  std::vector<unsigned long long> h(nbins);
+  rc = sync_and_check(c);
+  if (!rc && e == hipSuccess)
+    e = hipMemcpy(h.data(), hist, sizeof(unsigned long long) * nbins, hipMemcpyDeviceToHost);
+  dfree(c, hist);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(c, MD_EHIP, "md_rdf: HIP call failed");
+  const double dr = rmax / nbins, V = d.L * d.L * d.L, n = (double)d.n;
+  const double pi = 3.14159265358979323846;
+  for (int32_t b = 0; b < nbins; ++b) {
+    const double r0 = b * dr, r1 = (b + 1) * dr;
+    const double shell = 4.0 / 3.0 * pi * (r1 * r1 * r1 - r0 * r0 * r0);
+    g[b] = 2.0 * V * (double)h[b] / (n * n * shell);
   }
   return MD_OK;
 }

@@ -179,6 +179,15 @@ void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam)
 void launch_apply_lambda(hipStream_t s, int32_t ntiles, const Tile* tiles, int32_t stride,
                          double* vel, double* lam, int32_t nrep);
 
+// analysis.hip
+void launch_msd_ref(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
+                    const double4* pos, const int32_t* id, const int32_t* img, double* u0);
+void launch_msd(hipStream_t s, int32_t ntiles, int32_t nrep, const Tile* tiles,
+                const RepDesc* reps, const double4* pos, const int32_t* id, const int32_t* img,
+                const double* u0, double* part, double* out);
+void launch_rdf(hipStream_t s, const double4* pos, int32_t off, int32_t n, double L, double rmax,
+                int32_t nbins, unsigned long long* hist);
+
 // staged path (stage.h, nlist_staged.hip, force_staged.hip)
 struct RowTile;
 size_t nlist_staged_lds_bytes(int32_t lcap);

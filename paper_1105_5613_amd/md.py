@@ -26,7 +26,8 @@ MD_PATH_AUTO, MD_PATH_GATHER, MD_PATH_STAGED = 0, 1, 2
 EXPORTS = ["md_init", "md_destroy", "md_last_error", "md_set_state", "md_get_state",
            "md_build_cells", "md_forces", "md_get_forces", "md_step", "md_observables",
            "md_get_cells", "md_get_neighbors", "md_replica_info", "md_profile",
-           "md_profile_read", "md_list_stats"]
+           "md_profile_read", "md_list_stats", "md_autotune", "md_msd_reference", "md_msd",
+           "md_rdf"]
 
 
 class MDError(RuntimeError):
@@ -53,6 +54,12 @@ class Obs(C.Structure):
 
 
 OBS_KEYS = [f[0] for f in Obs._fields_]
+
+
+class Tune(C.Structure):
+    _fields_ = [("tpp", C.c_int32), ("unroll", C.c_int32), ("force_ms", C.c_double),
+                ("ntried", C.c_int32), ("tried_tpp", C.c_int32 * 16),
+                ("tried_unroll", C.c_int32 * 16), ("tried_ms", C.c_double * 16)]
 
 
 class Prof(C.Structure):
@@ -91,6 +98,10 @@ def lib():
         L.md_profile.argtypes = [vp, C.c_int32]
         L.md_profile_read.argtypes = [vp, C.POINTER(Prof)]
         L.md_list_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.md_autotune.argtypes = [vp, C.c_int32, C.POINTER(Tune)]
+        L.md_msd_reference.argtypes = [vp]
+        L.md_msd.argtypes = [vp, C.POINTER(C.c_double)]
+        L.md_rdf.argtypes = [vp, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_double)]
         for name in EXPORTS:
             if name != "md_last_error":
                 getattr(L, name).restype = C.c_int32
@@ -273,3 +284,26 @@ class System:
         mean, mx = C.c_double(), C.c_int32()
         self._check(lib().md_list_stats(self._h, rep, C.byref(mean), C.byref(mx)))
         return mean.value, mx.value
+
+    def autotune(self, reps=5):
+        """Pick the fastest force-kernel variant on the current state (md_autotune)."""
+        t = Tune()
+        self._check(lib().md_autotune(self._h, int(reps), C.byref(t)))
+        return {"tpp": t.tpp, "unroll": t.unroll, "force_ms": t.force_ms,
+                "tried": [(t.tried_tpp[k], t.tried_unroll[k], t.tried_ms[k])
+                          for k in range(t.ntried)]}
+
+    # -- glass-study observables -------------------------------------------------
+    def msd_reference(self):
+        self._check(lib().md_msd_reference(self._h))
+
+    def msd(self):
+        out = (C.c_double * self.nrep)()
+        self._check(lib().md_msd(self._h, out))
+        return np.array(out[:])
+
+    def rdf(self, rep=0, rmax=4.0, nbins=400):
+        g = np.zeros(nbins)
+        self._check(lib().md_rdf(self._h, rep, float(rmax), int(nbins),
+                                 g.ctypes.data_as(C.POINTER(C.c_double))))
+        return g
