@@ -104,7 +104,8 @@ typedef struct {
   double T;         /* 2 ke / (3 n - 3) */
   double P;         /* (2 ke + W) / (3 V) */
   double E;         /* ke + pe */
-  double max_disp;  /* largest displacement since the last list build */
+  double max_disp;  /* largest |x - x_ref| after this step's drift (x_ref: positions at
+                       the last list build), before any rebuild it triggers */
   double T_target;  /* thermostat target of the step (0 for NVE) */
   int64_t step;     /* steps taken since md_set_state */
   int64_t n_rebuild;/* list builds since md_set_state */

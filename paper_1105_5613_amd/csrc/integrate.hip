@@ -24,12 +24,13 @@ __global__ __launch_bounds__(kTile) void k_kick_drift(
     double* __restrict__ vel, const FT* __restrict__ frc, const double* __restrict__ xref,
     int32_t stride, double dt,
     const double* __restrict__ lam, int32_t* __restrict__ rebuild,
-    unsigned long long* __restrict__ maxd2, DevState* st) {
+    double* __restrict__ dmax, DevState* st) {
   __shared__ double s_im[4];
   __shared__ double s_red[kTile / 64];
   if (threadIdx.x < 4) s_im[threadIdx.x] = tab->inv_mass[threadIdx.x];
   __syncthreads();
-  const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
+  const Tile t = tiles[tb];
   const int32_t i = t.start + threadIdx.x;
   double d2 = 0.0;
   if (i < t.end) {
@@ -69,8 +70,7 @@ __global__ __launch_bounds__(kTile) void k_kick_drift(
       rebuild[t.rep] = 1;
       st->any_rebuild = 1;
     }
-    // non-negative doubles order like their bit patterns
-    atomicMax(&maxd2[t.rep], (unsigned long long)__double_as_longlong(m));
+    dmax[tb] = m;  // the per-replica maximum is taken by the reduction
   }
 }
 
@@ -88,13 +88,13 @@ __device__ inline void neumaier(double& s, double& c, double x) {
 constexpr int kRedThreads = 1024;
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restrict__ reps,
                                                         const double* __restrict__ part,
+                                                        const double* __restrict__ dmax,
                                                         int32_t step, ThermoArgs ta,
                                                         int64_t* __restrict__ kcall,
                                                         double* __restrict__ lam,
                                                         int32_t* __restrict__ rebuild,
-                                                        unsigned long long* __restrict__ maxd2,
                                                         md_obs* __restrict__ obs, DevState* st) {
-  __shared__ double red[3][kRedThreads];
+  __shared__ double red[4][kRedThreads];
   const int32_t r = blockIdx.x;
   const RepDesc R = reps[r];
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
@@ -102,10 +102,17 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
   for (int32_t b = b0 + threadIdx.x; b < b1; b += kRedThreads)
     for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
   for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
+  // largest squared displacement of this step's drift (tile maxima)
+  double m = 0.0;
+  if (step)
+    for (int32_t b = R.tile0 + threadIdx.x; b < R.tile1; b += kRedThreads) m = fmax(m, dmax[b]);
+  red[3][threadIdx.x] = m;
   __syncthreads();
   for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
-    if (threadIdx.x < h)
+    if (threadIdx.x < h) {
       for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + h]);
+    }
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
@@ -115,8 +122,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
   o.pe = pe;
   o.virial = w;
   o.T_target = 0.0;
-  const double md2 = __longlong_as_double((long long)maxd2[r]);
-  o.max_disp = sqrt(md2);
+  if (step) o.max_disp = sqrt(red[3][0]);
   if (step) {
     const int64_t k = ++kcall[r];
     if (ta.thermo) {
@@ -137,7 +143,6 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
     if (rebuild[r]) {
       o.n_rebuild += 1;
       rebuild[r] = 0;
-      maxd2[r] = 0ull;
     }
     if (r == 0) st->any_rebuild = 0;
   }
@@ -155,13 +160,12 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
   }
 }
 
-__global__ void k_after_build(int32_t nrep, int32_t* rebuild, unsigned long long* maxd2,
-                              md_obs* obs, DevState* st) {
+__global__ void k_after_build(int32_t nrep, int32_t* rebuild, md_obs* obs, DevState* st) {
   const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nrep && rebuild[r]) {
     obs[r].n_rebuild += 1;
+    obs[r].max_disp = 0.0;
     rebuild[r] = 0;
-    maxd2[r] = 0ull;
   }
   if (r == 0) st->any_rebuild = 0;
 }
@@ -199,11 +203,11 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab, double4* pos,
                        float4* pos16, double* vel, const void* frc, const double* xref,
                        int32_t stride, double dt, const double* lam, int32_t* rebuild,
-                       unsigned long long* maxd2, DevState* st) {
+                       double* dmax, DevState* st) {
 #define KD(FT, TH)                                                                         \
   k_kick_drift<FT, TH><<<ntiles, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, vel,         \
                                                 (const FT*)frc, xref, stride, dt, lam,     \
-                                                rebuild, maxd2, st)
+                                                rebuild, dmax, st)
   if (mixed) {
     if (thermo) KD(float, true); else KD(float, false);
   } else {
@@ -213,15 +217,14 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
 }
 
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
-                   int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
-                   int32_t* rebuild, unsigned long long* maxd2, md_obs* obs, DevState* st) {
-  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, step, ta, kcall, lam, rebuild, maxd2, obs,
-                                        st);
+                   const double* dmax, int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
+                   int32_t* rebuild, md_obs* obs, DevState* st) {
+  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, dmax, step, ta, kcall, lam, rebuild, obs, st);
 }
 
-void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, unsigned long long* maxd2,
-                        md_obs* obs, DevState* st) {
-  k_after_build<<<nblk(nrep, 256), 256, 0, s>>>(nrep, rebuild, maxd2, obs, st);
+void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* obs,
+                        DevState* st) {
+  k_after_build<<<nblk(nrep, 256), 256, 0, s>>>(nrep, rebuild, obs, st);
 }
 
 void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam) {

@@ -44,7 +44,7 @@ struct md_ctx_s {
   int32_t* ncount = nullptr;
   double* part = nullptr;
   int32_t* rebuild = nullptr;
-  unsigned long long* maxd2 = nullptr;
+  double* dmax = nullptr;   // [ntiles] per-tile max of the last drift
   md_obs* obs = nullptr;
   int64_t* kcall = nullptr;
   double* lam = nullptr;
@@ -241,7 +241,7 @@ md_status build_all(md_ctx c) {
   for (int attempt = 0; attempt < 2; ++attempt) {
     launch_mark_rebuild(c->stream, c->nrep, c->rebuild, c->st);
     run_chain(c, c->stream);
-    launch_after_build(c->stream, c->nrep, c->rebuild, c->maxd2, c->obs, c->st);
+    launch_after_build(c->stream, c->nrep, c->rebuild, c->obs, c->st);
     md_status rc = sync_and_check(c);
     if (rc == MD_OK) {
       c->built = true;
@@ -262,15 +262,15 @@ ThermoArgs no_thermo() {
 
 void launch_forces0(md_ctx c) {
   launch_forces(c, 0, c->stream);
-  launch_reduce(c->stream, c->nrep, c->reps, c->part, 0, no_thermo(), c->kcall, c->lam,
-                c->rebuild, c->maxd2, c->obs, c->st);
+  launch_reduce(c->stream, c->nrep, c->reps, c->part, c->dmax, 0, no_thermo(), c->kcall, c->lam,
+                c->rebuild, c->obs, c->st);
 }
 
 
 // One velocity-Verlet step on stream s (also used while capturing a graph).
 md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t thermo, int32_t k) {
   launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16,
-                    c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->maxd2,
+                    c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->dmax,
                     c->st);
   run_chain(c, s);
   const bool timed = c->prof_every > 0 && (k + 1) % c->prof_every == 0;
@@ -283,7 +283,7 @@ md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t th
     HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
     c->ev_used += 2;
   }
-  launch_reduce(s, c->nrep, c->reps, c->part, 1, ta, c->kcall, c->lam, c->rebuild, c->maxd2,
+  launch_reduce(s, c->nrep, c->reps, c->part, c->dmax, 1, ta, c->kcall, c->lam, c->rebuild,
                 c->obs, c->st);
   return MD_OK;
 }
@@ -572,7 +572,7 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
   ALLOC(c->ncount, N);
   ALLOC(c->part, 4 * std::max((size_t)c->ntiles * 8, (size_t)c->nrt));
   ALLOC(c->rebuild, (size_t)nrep);
-  ALLOC(c->maxd2, (size_t)nrep);
+  ALLOC(c->dmax, (size_t)c->ntiles);
   ALLOC(c->obs, (size_t)nrep);
   ALLOC(c->kcall, (size_t)nrep);
   ALLOC(c->lam, (size_t)nrep);
@@ -591,7 +591,6 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
             hipMemset(c->st, 0, sizeof(DevState)) == hipSuccess &&
             hipMemset(c->counts, 0, sizeof(int32_t) * c->ncells) == hipSuccess &&
             hipMemset(c->rebuild, 0, sizeof(int32_t) * nrep) == hipSuccess &&
-            hipMemset(c->maxd2, 0, sizeof(unsigned long long) * nrep) == hipSuccess &&
             hipMemset(c->obs, 0, sizeof(md_obs) * nrep) == hipSuccess &&
             hipMemset(c->kcall, 0, sizeof(int64_t) * nrep) == hipSuccess &&
             hipMemset(c->frc, 0, (c->mixed ? 4 : 8) * 3 * S) == hipSuccess;
@@ -621,7 +620,6 @@ md_status md_set_state(md_ctx c, const double* x, const double* v, const int32_t
   launch_set_state(c->stream, c->ntot, c->stride, x, v, type, c->p.ntypes, c->pos, c->vel, c->id,
                    c->img, c->st);
   HIPCHECK(c, hipMemsetAsync(c->obs, 0, sizeof(md_obs) * c->nrep, c->stream));
-  HIPCHECK(c, hipMemsetAsync(c->maxd2, 0, sizeof(unsigned long long) * c->nrep, c->stream));
   HIPCHECK(c, hipMemsetAsync(c->frc, 0, (c->mixed ? 4 : 8) * 3 * (size_t)c->stride, c->stream));
   md_status rc = sync_and_check(c);
   // positions are checked against the box at the first wrap

@@ -156,7 +156,7 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab,
                        double4* pos, float4* pos16, double* vel, const void* frc,
                        const double* xref, int32_t stride, double dt, const double* lam,
-                       int32_t* rebuild, unsigned long long* maxd2, DevState* st);
+                       int32_t* rebuild, double* dmax, DevState* st);
 struct ThermoArgs {
   const double* T0;    // [nrep]
   const double* T1;    // [nrep]
@@ -169,12 +169,13 @@ struct ThermoArgs {
 };
 // step = 0: observables of the current state only; step = 1: end of a step
 // part holds one (pe, w, ke) triple per force block; replica r owns blocks
-// [fb0, fb1).
+// [fb0, fb1).  dmax holds the kick/drift tile maxima of |x - x_ref|^2
+// (tiles [tile0, tile1) of replica r), read when step = 1.
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
-                   int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
-                   int32_t* rebuild, unsigned long long* maxd2, md_obs* obs, DevState* st);
-void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild,
-                        unsigned long long* maxd2, md_obs* obs, DevState* st);
+                   const double* dmax, int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
+                   int32_t* rebuild, md_obs* obs, DevState* st);
+void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* obs,
+                        DevState* st);
 void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam);
 void launch_apply_lambda(hipStream_t s, int32_t ntiles, const Tile* tiles, int32_t stride,
                          double* vel, double* lam, int32_t nrep);

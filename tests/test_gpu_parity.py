@@ -142,6 +142,12 @@ def test_short_trajectory_matches_oracle(torch_cuda):
     assert np.max(np.abs(v.cpu().numpy() - vo)) < 1e-8
     assert np.allclose(log["E"][:, 0], ref["E"], rtol=1e-10)
     assert np.array_equal(log["step"][:, 0], np.arange(1, 21))
+    # the skin rule: same displacement maxima, rebuilds at the same steps
+    assert np.allclose(log["max_disp"][:, 0], np.sqrt(ref["max_disp2"]), rtol=1e-8, atol=0)
+    nb = log["n_rebuild"][:, 0]
+    assert np.array_equal(np.diff(np.concatenate([[nb[0] - ref["rebuilt"][0]], nb])),
+                          ref["rebuilt"])
+    assert ref["rebuilt"].sum() >= 2
 
 
 @pytest.mark.parametrize("path", ["gather", "staged"])
