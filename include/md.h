@@ -63,10 +63,11 @@ enum { MD_TRUNC_SHIFTED_FORCE = 0, MD_TRUNC_SHIFT = 1 };
 enum { MD_FP64 = 0, MD_MIXED = 1 };
 /* Kernel path.  GATHER: one thread group per particle gathers neighbour
  * positions from global memory; list entries are 32-bit indices with a
- * periodic-image code; works for any box.  STAGED: one block per row of
- * cells stages the neighbourhood (with periodic shifts applied) in LDS and
- * list entries are 16-bit LDS slots; needs >= 3 cells per box side.  AUTO
- * is GATHER, the faster path on MI355X at the measured sizes. */
+ * periodic-image code; works for any box.  STAGED: one block per row tile
+ * of cells (about 128 home particles) copies the tile's 27-piece
+ * neighbourhood, with periodic shifts applied, into LDS once per force
+ * launch, and list entries are 16-bit LDS slots; needs >= 3 cells per box
+ * side.  AUTO is GATHER. */
 enum { MD_PATH_AUTO = 0, MD_PATH_GATHER = 1, MD_PATH_STAGED = 2 };
 #define MD_MAXT 4
 
@@ -86,11 +87,11 @@ typedef struct {
   double dt;          /* time step */
   int32_t max_neighbors; /* neighbour capacity per particle; 0 = from density */
   int32_t graph_steps;   /* steps per captured hipGraph in md_step; 0 = direct */
-  int32_t tpp;           /* lanes per particle in the force kernel (1,2,4,8); 0 = auto */
+  int32_t tpp;           /* lanes per particle in the force kernel (1,2,4,8; staged
+                            path 1,2,4); 0 = auto */
   int32_t unroll;        /* list slots gathered per pipelined chunk in the force
                             kernel (1,2,4,8); 0 = auto */
   int32_t path;          /* MD_PATH_AUTO, MD_PATH_GATHER or MD_PATH_STAGED */
-  int32_t tile_threads;  /* staged path: threads per row-tile block (128, 256); 0 = auto */
   int32_t tile_cells;    /* staged path: cells per row tile (1..64); 0 = auto */
   int32_t stage_slots;   /* staged path: LDS slots per tile (>= 64); slots beyond are
                             read from global memory; 0 = auto */
@@ -199,7 +200,7 @@ md_status md_profile(md_ctx ctx, int32_t every);
 md_status md_profile_read(md_ctx ctx, md_prof* out);
 
 /* Autotuner: times every force-kernel variant of the context's path (lanes
- * per particle x unroll on the gather path; unroll on the staged path) on
+ * per particle x unroll) on
  * the current state, `reps` launches each, with hipEvents on the context
  * stream, keeps the fastest and recomputes forces and observables with it.
  * Positions and velocities are not changed.  Synchronises. */

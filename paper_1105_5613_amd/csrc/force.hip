@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kTile) void k_force(
           int32_t mx = cxi - (int32_t)(wj & 1023u), my = cyi - (int32_t)((wj >> 10) & 1023u),
                   mz = czi - (int32_t)((wj >> 20) & 1023u);
           float ddx = pi.x - q[u].x, ddy = pi.y - q[u].y, ddz = pi.z - q[u].z;
-          if (e[u] >> kIdxBits) {
+          if (__ballot(e[u] >> kIdxBits)) {  // wave-uniform, as in the FP64 form
             const int32_t sx = decode_shift(e[u], 26), sy = decode_shift(e[u], 28),
                           sz = decode_shift(e[u], 30);
             mx -= sx * nc;
@@ -206,8 +206,9 @@ __global__ __launch_bounds__(kTile) void k_force(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           double dx = p.x - q[u].x, dy = p.y - q[u].y, dz = p.z - q[u].z;
-          if (e[u] >> kIdxBits) {
-            // x_i - (x_j + s L)
+          // x_i - (x_j + s L); wave-uniform test: only waves with a periodic
+          // partner pay for the shift (s = 0 leaves d unchanged)
+          if (__ballot(e[u] >> kIdxBits)) {
             dx -= (double)decode_shift(e[u], 26) * L;
             dy -= (double)decode_shift(e[u], 28) * L;
             dz -= (double)decode_shift(e[u], 30) * L;

@@ -1,10 +1,16 @@
 // force_staged.hip -- the pair-force hot spot on the staged path: one block
-// per row tile stages the tile's neighbourhood (positions with their periodic
-// shift applied, FP64) into LDS one z-slab of rows at a time, and each home
-// particle walks the part of its 16-bit slot list that belongs to the slab.  Same pair arithmetic as force.hip: shifted-force
-// Eq. (3) on Eq. (1)/(2), FP64 with an FP32-seeded two-step Newton-Raphson
-// 1/r, or FP32 pair math from the FP64 displacement (mixed); per-particle
-// energy/virial halves widened to FP64 and reduced per tile.
+// per row tile (stage.h) copies the tile's whole 27-piece neighbourhood
+// (positions with their periodic shift applied, FP64) into LDS with
+// coalesced loads, then every home particle walks its 16-bit slot list
+// against LDS instead of gathering its partners from global memory.  TPP
+// lanes per particle take interleaved list slots and combine their sums with
+// cross-lane shuffles; the list walk is software-pipelined by U slots.
+//
+// Pair arithmetic as in force.hip: shifted-force Eq. (3) on Eq. (1)/(2);
+// FP64 with an FP32-seeded two-step Newton-Raphson 1/r, or FP32 pair math
+// from the FP64 displacement (mixed); per-particle energy and virial halves
+// reduced per block in FP64.  Also holds the decode of staged entries back to
+// sorted particle indices (neighbour-list parity hook).
 #include "stage.h"
 
 namespace mdk {
@@ -51,15 +57,18 @@ __device__ inline void block_sum3(double& a, double& b, double& c) {
   }
 }
 
-template <bool MIXED, int MODE, int BT, int U>
-__global__ __launch_bounds__(BT) void k_force_staged(
+// home particles handled per group: kStageHomes x TPP threads per block
+constexpr int kStageHomes = 128;
+
+template <bool MIXED, int MODE, int TPP, int U>
+__global__ __launch_bounds__(kStageHomes* TPP) void k_force_staged(
     const RowTile* __restrict__ rtiles, const RepDesc* __restrict__ reps,
     const PairTab* __restrict__ tab, const int32_t* __restrict__ cell_start,
     const double4* __restrict__ pos, double* __restrict__ vel, void* __restrict__ frc_,
-    const uint16_t* __restrict__ nbr, const int32_t* __restrict__ ncount,
-    const uint32_t* __restrict__ nsplit, int32_t stride, int32_t cap, int32_t lcap, double dt,
-    double* __restrict__ part, DevState* st) {
+    const uint16_t* __restrict__ nbr, const int32_t* __restrict__ ncount, int32_t stride,
+    int32_t cap, int32_t lcap, double dt, double* __restrict__ part, DevState* st) {
   using T = typename std::conditional<MIXED, float, double>::type;
+  constexpr int BT = kStageHomes * TPP;
   __shared__ StageLayout S;
   __shared__ PairLds<T> P;
   __shared__ double s_mass[4];
@@ -81,92 +90,96 @@ __global__ __launch_bounds__(BT) void k_force_staged(
   }
   if (threadIdx.x < 4) s_mass[threadIdx.x] = tab->mass[threadIdx.x];
   build_layout(S, Tl, R, cell_start);
-  double* xs = dyn;
-  double* ys = xs + lcap;
-  double* zs = ys + lcap;
+  double2* xy = (double2*)dyn;
+  double* zz = (double*)(xy + lcap);
+  stage_all(S, pos, lcap, xy, zz);
 
   double pe = 0.0, w = 0.0, ke = 0.0;
   const int32_t nh = S.home1 - S.home0;
-  // home particles in groups of BT (one per thread); the passes restage per group
-  for (int32_t g0 = 0; g0 < nh; g0 += BT) {
-    const int32_t li = g0 + (int32_t)threadIdx.x;
+  const int32_t lane_p = (int32_t)threadIdx.x % TPP;
+  for (int32_t g0 = 0; g0 < nh; g0 += kStageHomes) {
+    const int32_t li = g0 + (int32_t)threadIdx.x / TPP;
     const bool mine = li < nh;
     const int32_t i = S.home0 + (mine ? li : 0);
     const double4 p = pos[i];
     const int32_t ti = (int32_t)p.w;
-    const int32_t n = mine ? (ncount[i] < cap ? ncount[i] : cap) : 0;
-    const uint32_t sp = mine ? nsplit[i] : 0u;
-    const int32_t n0 = (int32_t)(sp & 0xffffu), n1 = (int32_t)(sp >> 16);
+    int32_t n = mine ? ncount[i] : 0;
+    n = n < cap ? n : cap;
     const uint16_t* row = nbr + i;
     T fx = 0, fy = 0, fz = 0, pe_i = 0, w_i = 0;
-    for (int pass = 0; pass < 3; ++pass) {
-      const int32_t base = pass_base(S, pass);
-      stage<false>(S, pass, pos, lcap, xs, ys, zs, nullptr);
-      int32_t k0 = pass == 0 ? 0 : (pass == 1 ? n0 : n0 + n1);
-      int32_t k1 = pass == 0 ? n0 : (pass == 1 ? n0 + n1 : n);
-      k0 = k0 < n ? k0 : n;
-      k1 = k1 < n ? k1 : n;
-      // entries of the next chunk are loaded ahead; padding repeats the last
-      // slot and is masked out
-      uint32_t e[U];
+    // list slots of the next chunk are loaded ahead; slots past n repeat
+    // slot 0 and are masked out
+    uint32_t e[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) e[u] = k0 + u < k1 ? (uint32_t)row[(size_t)(k0 + u) * stride] : 0u;
-      for (int32_t kk = k0; kk < k1; kk += U) {
-        uint32_t en[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int32_t k = kk + U + u;
-          en[u] = k < k1 ? (uint32_t)row[(size_t)k * stride] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int32_t v = (int32_t)(e[u] & 0x3fffu);
-          double qx, qy, qz;
-          if (v < lcap) {
-            qx = xs[v];
-            qy = ys[v];
-            qz = zs[v];
-          } else {
-            const double4 q = fetch_slot(S, pos, v + base);
-            qx = q.x;
-            qy = q.y;
-            qz = q.z;
-          }
-          const int32_t ab = ti * 4 + (int32_t)(e[u] >> 14);
-          const T dx = (T)(p.x - qx), dy = (T)(p.y - qy), dz = (T)(p.z - qz);
-          const T r2 = dx * dx + dy * dy + dz * dz;
-          if (kk + u < k1 && r2 < P.rc2[ab]) {
-            T rinv;
-            if constexpr (MIXED)
-              rinv = __builtin_amdgcn_rsqf(r2);
-            else
-              rinv = rsqrt_nr(r2);
-            const T r2inv = rinv * rinv;
-            const T sr2 = P.sig2[ab] * r2inv;
-            const T sr6 = sr2 * sr2 * sr2;
-            const T sr12 = sr6 * sr6;
-            const T fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
-            fx += fr * dx;
-            fy += fr * dy;
-            fz += fr * dz;
-            pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
-                    (r2 * rinv - P.rc[ab]) * P.fs[ab];
-            w_i += fr * r2;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) e[u] = en[u];
-      }
-      __syncthreads();  // the next pass overwrites the staged rows
+    for (int u = 0; u < U; ++u) {
+      const int32_t k = lane_p + u * TPP;
+      e[u] = k < n ? (uint32_t)row[(size_t)k * stride] : 0u;
     }
-    if (mine) {
+    for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
+      uint32_t en[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t k = k0 + (U + u) * TPP;
+        en[u] = k < n ? (uint32_t)row[(size_t)k * stride] : 0u;
+      }
+      double qx[U], qy[U], qz[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t v = (int32_t)(e[u] & 0x3fffu);
+        if (v < lcap) {
+          const double2 a = xy[v];
+          qx[u] = a.x;
+          qy[u] = a.y;
+          qz[u] = zz[v];
+        } else {
+          const double4 q = fetch_slot(S, pos, v);
+          qx[u] = q.x;
+          qy[u] = q.y;
+          qz[u] = q.z;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t ab = ti * 4 + (int32_t)(e[u] >> 14);
+        const T dx = (T)(p.x - qx[u]), dy = (T)(p.y - qy[u]), dz = (T)(p.z - qz[u]);
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
+          T rinv;
+          if constexpr (MIXED)
+            rinv = __builtin_amdgcn_rsqf(r2);
+          else
+            rinv = rsqrt_nr(r2);
+          const T r2inv = rinv * rinv;
+          const T sr2 = P.sig2[ab] * r2inv;
+          const T sr6 = sr2 * sr2 * sr2;
+          const T sr12 = sr6 * sr6;
+          const T fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
+          fx += fr * dx;
+          fy += fr * dy;
+          fz += fr * dz;
+          pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
+                  (r2 * rinv - P.rc[ab]) * P.fs[ab];
+          w_i += fr * r2;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) e[u] = en[u];
+    }
+    // combine the TPP partial sums (fixed order: deterministic)
+#pragma unroll
+    for (int d = 1; d < TPP; d <<= 1) {
+      fx += __shfl_xor(fx, d, 64);
+      fy += __shfl_xor(fy, d, 64);
+      fz += __shfl_xor(fz, d, 64);
+    }
+    pe += 0.5 * (double)pe_i;
+    w += 0.5 * (double)w_i;
+    if (mine && lane_p == 0) {
       if (!isfinite((double)(fx + fy + fz))) atomicOr(&st->err, kErrNonFinite);
       T* frc = (T*)frc_;
       frc[i] = fx;
       frc[stride + i] = fy;
       frc[2 * (size_t)stride + i] = fz;
-      pe += 0.5 * (double)pe_i;
-      w += 0.5 * (double)w_i;
       const double m = s_mass[ti];
       double v0 = vel[i], v1 = vel[stride + i], v2 = vel[2 * (size_t)stride + i];
       if (MODE == 1) {
@@ -190,40 +203,73 @@ __global__ __launch_bounds__(BT) void k_force_staged(
   }
 }
 
+// Staged entries -> sorted particle indices (parity hook only).
+__global__ __launch_bounds__(256) void k_decode_staged(
+    const RowTile* __restrict__ rtiles, const RepDesc* __restrict__ reps,
+    const int32_t* __restrict__ cell_start, int32_t stride, int32_t rows,
+    const uint16_t* __restrict__ nbr, const int32_t* __restrict__ ncount,
+    uint32_t* __restrict__ out) {
+  __shared__ StageLayout S;
+  const RowTile T = rtiles[blockIdx.x];
+  const RepDesc R = reps[T.rep];
+  build_layout(S, T, R, cell_start);
+  const int32_t nh = S.home1 - S.home0;
+  for (int32_t li = threadIdx.x; li < nh; li += blockDim.x) {
+    const int32_t i = S.home0 + li;
+    int32_t n = ncount[i];
+    n = n < rows ? n : rows;
+    for (int32_t k = 0; k < n; ++k) {
+      int32_t v = nbr[(size_t)k * stride + i] & 0x3fff;
+      v = v < S.total ? v : S.total - 1;  // only after a reported overflow
+      const int p = piece_of(S, v);
+      out[(size_t)k * stride + i] = (uint32_t)(S.pc_g[p] + (v - S.pc_l[p]));
+    }
+  }
+}
+
 }  // namespace
 
 size_t force_staged_lds_bytes(int32_t lcap) { return (size_t)lcap * 24; }
 
-void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t bt, int32_t unroll,
+int32_t staged_homes_per_group() { return kStageHomes; }
+
+void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
                          int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
                          const PairTab* tab, const int32_t* cell_start, const double4* pos,
                          double* vel, void* frc, const uint16_t* nbr, const int32_t* ncount,
-                         const uint32_t* nsplit, int32_t stride, int32_t cap, int32_t lcap,
-                         double dt, double* part, DevState* st) {
+                         int32_t stride, int32_t cap, int32_t lcap, double dt, double* part,
+                         DevState* st) {
   const size_t lds = force_staged_lds_bytes(lcap);
-#define KS(M, MO, B, UU)                                                                       \
-  k_force_staged<M, MO, B, UU><<<nrt, B, lds, s>>>(rtiles, reps, tab, cell_start, pos, vel, frc, \
-                                                  nbr, ncount, nsplit, stride, cap, lcap, dt,  \
-                                                  part, st)
-#define BYU(M, MO)                                 \
-  do {                                             \
-    if (bt == 128) {                               \
-      if (unroll == 8) KS(M, MO, 128, 8);          \
-      else if (unroll == 2) KS(M, MO, 128, 2);     \
-      else KS(M, MO, 128, 4);                      \
-    } else {                                       \
-      if (unroll == 8) KS(M, MO, 256, 8);          \
-      else if (unroll == 2) KS(M, MO, 256, 2);     \
-      else KS(M, MO, 256, 4);                      \
-    }                                              \
+#define KS(M, MO, TP, UU)                                                                    \
+  k_force_staged<M, MO, TP, UU><<<nrt, kStageHomes * TP, lds, s>>>(                          \
+      rtiles, reps, tab, cell_start, pos, vel, frc, nbr, ncount, stride, cap, lcap, dt, part, \
+      st)
+#define BYTU(M, MO)                                   \
+  do {                                                \
+    if (tpp == 1) {                                   \
+      if (unroll == 8) KS(M, MO, 1, 8);               \
+      else KS(M, MO, 1, 4);                           \
+    } else if (tpp == 4) {                            \
+      KS(M, MO, 4, 2);                                \
+    } else {                                          \
+      if (unroll == 2) KS(M, MO, 2, 2);               \
+      else if (unroll == 8) KS(M, MO, 2, 8);          \
+      else KS(M, MO, 2, 4);                           \
+    }                                                 \
   } while (0)
   if (mixed) {
-    if (mode) BYU(true, 1); else BYU(true, 0);
+    if (mode) BYTU(true, 1); else BYTU(true, 0);
   } else {
-    if (mode) BYU(false, 1); else BYU(false, 0);
+    if (mode) BYTU(false, 1); else BYTU(false, 0);
   }
-#undef BYU
+#undef BYTU
 #undef KS
+}
+
+void launch_decode_staged(hipStream_t s, int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
+                          const int32_t* cell_start, int32_t stride, int32_t rows,
+                          const uint16_t* nbr, const int32_t* ncount, uint32_t* out) {
+  k_decode_staged<<<nrt, 256, 0, s>>>(rtiles, reps, cell_start, stride, rows, nbr, ncount, out);
 }
 
 }  // namespace mdk

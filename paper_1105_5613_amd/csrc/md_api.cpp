@@ -19,12 +19,12 @@ struct md_ctx_s {
   int32_t nrep = 0, ntot = 0, stride = 0, ncells = 0, ntiles = 0, cap = 0, tpp = 1, unroll = 4;
   int32_t mixed = 0;
   // staged path (row tiles with LDS-staged neighbourhoods)
-  int32_t staged = 0, bt = 256, nrt = 0, lcap_nl = 0, lcap_f = 0;
+  int32_t staged = 0, nrt = 0, lcap_f = 0;
   int32_t any_single = 0, any_multi = 0;  // replicas with one cell / with >= 3 per side
   std::vector<RowTile> rtiles_h;
   RowTile* rtiles = nullptr;
   uint16_t* nbr16 = nullptr;
-  uint32_t* nsplit = nullptr;  // staged path: list lengths of passes 0 and 1
+  int32_t* cell_tile = nullptr;  // staged path: row tile of each cell
   hipStream_t stream = nullptr;
   std::vector<RepDesc> reps_h;
   std::vector<Tile> tiles_h;
@@ -158,8 +158,6 @@ md_status validate(const md_params* p, std::string* why) {
   if (p->unroll != 0 && p->unroll != 1 && p->unroll != 2 && p->unroll != 4 && p->unroll != 8)
     return *why = "unroll must be 0, 1, 2, 4 or 8", MD_EINVAL;
   if (p->path < MD_PATH_AUTO || p->path > MD_PATH_STAGED) return *why = "unknown path", MD_EINVAL;
-  if (p->tile_threads != 0 && p->tile_threads != 128 && p->tile_threads != 256)
-    return *why = "tile_threads must be 0, 128 or 256", MD_EINVAL;
   if (p->tile_cells < 0 || p->tile_cells > kMaxRowCells)
     return *why = "tile_cells must be 0..64", MD_EINVAL;
   if (p->stage_slots != 0 && p->stage_slots < 64) return *why = "stage_slots must be 0 or >= 64", MD_EINVAL;
@@ -193,9 +191,9 @@ void run_chain(md_ctx c, hipStream_t s) {
   launch_cell_gather(s, c->ncells, c->cell_rep, c->rebuild, c->cell_start, c->tmp_src, c->stride,
                      c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp);
   if (c->staged)
-    launch_nlist_staged(s, c->bt, c->nrt, c->rtiles, c->reps, c->rebuild, c->tab, c->cell_start,
-                        c->stride, c->cap, c->lcap_nl, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos,
-                        c->vel, c->id, c->xref, c->nbr16, c->ncount, c->nsplit, c->st);
+    launch_nlist_tiles(s, c->ncells, c->cell_rep, c->reps, c->rebuild, c->tab, c->cell_start,
+                       c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
+                       c->xref, c->nbr16, c->ncount, c->st, c->cell_tile, c->rtiles);
   else
     launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->p.ntypes, c->cell_start,
                  c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
@@ -205,9 +203,9 @@ void run_chain(md_ctx c, hipStream_t s) {
 
 void launch_forces(md_ctx c, int32_t mode, hipStream_t s) {
   if (c->staged)
-    launch_force_staged(s, c->mixed, mode, c->bt, c->unroll, c->nrt, c->rtiles, c->reps,
+    launch_force_staged(s, c->mixed, mode, c->tpp, c->unroll, c->nrt, c->rtiles, c->reps,
                         c->tab, c->cell_start, c->pos, c->vel, c->frc, c->nbr16, c->ncount,
-                        c->nsplit, c->stride, c->cap, c->lcap_f, c->p.dt, c->part, c->st);
+                        c->stride, c->cap, c->lcap_f, c->p.dt, c->part, c->st);
   else
     launch_force(s, c->mixed, mode, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps,
                  c->tab, c->pos, c->pos16, c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap,
@@ -429,7 +427,6 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
         return fail(nullptr, MD_EINVAL,
                     "mixed precision on the gather path supports up to 1023 cells per side");
       }
-  c->bt = p->tile_threads ? p->tile_threads : 256;
   int32_t lds_max = 65536;
   {
     int dev = 0, v = 0;
@@ -441,13 +438,20 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     lds_max = std::min(lds_max, 65536);  // stay within the default per-block limit
   }
   if (c->staged) {
+    if (c->tpp == 8) {
+      delete c;
+      return fail(nullptr, MD_EINVAL, "the staged path takes tpp 1, 2 or 4");
+    }
+    // row tiles of about kStageHomes home particles; LDS holds the tile's
+    // 9 x (nx + 2) cells with 30 % headroom (denser tiles spill to global)
+    const int32_t homes = staged_homes_per_group();
     double need = 0.0;
     for (int r = 0; r < nrep; ++r) {
       RepDesc& d = c->reps_h[r];
       const int32_t nc = d.nc;
       const double ppc = (double)d.n / ((double)nc * nc * nc);
       int32_t cpt = p->tile_cells;
-      if (cpt <= 0) cpt = (int32_t)std::lround(0.8 * c->bt / ppc);
+      if (cpt <= 0) cpt = (int32_t)std::floor(0.85 * homes / ppc);
       cpt = std::max(1, std::min(cpt, std::min(nc, (int32_t)kMaxRowCells)));
       const int32_t ntr = (nc + cpt - 1) / cpt;
       d.fb0 = (int32_t)c->rtiles_h.size();
@@ -463,17 +467,13 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
           c->rtiles_h.push_back(rt);
         }
       d.fb1 = (int32_t)c->rtiles_h.size();
-      need = std::max(need, 3.0 * (nxmax + 2) * ppc);  // one pass: 3 rows
+      need = std::max(need, 9.0 * (nxmax + 2) * ppc);
     }
     c->nrt = (int32_t)c->rtiles_h.size();
     const int32_t want = (int32_t)((int64_t)std::ceil(1.3 * need + 64) / 64 * 64);
-    const int32_t room = lds_max - 8192;  // static LDS of the kernels
+    const int32_t room = lds_max - 8192;  // static LDS of the kernel
     c->lcap_f = std::max(64, std::min(want, (int32_t)(room / 24)));
-    c->lcap_nl = std::max(64, std::min(want, (int32_t)(room / 25)));
-    if (p->stage_slots > 0) {
-      c->lcap_f = std::min(c->lcap_f, p->stage_slots);
-      c->lcap_nl = std::min(c->lcap_nl, p->stage_slots);
-    }
+    if (p->stage_slots > 0) c->lcap_f = std::min(c->lcap_f, p->stage_slots);
   } else {
     for (RepDesc& d : c->reps_h) {
       d.fb0 = d.tile0 * c->tpp;
@@ -564,7 +564,7 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
   ALLOC(c->img, 3 * N);
   if (c->staged) {
     ALLOC(c->nbr16, (size_t)c->cap * S);
-    ALLOC(c->nsplit, N);
+    ALLOC(c->cell_tile, (size_t)c->ncells);
     ALLOC(c->rtiles, (size_t)c->nrt);
   } else {
     ALLOC(c->nbr, (size_t)c->cap * S);
@@ -582,12 +582,23 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
   };
   std::vector<double> ones(nrep, 1.0);
+  std::vector<int32_t> cell_tile;
+  if (c->staged) {
+    cell_tile.assign(c->ncells, 0);
+    for (int32_t t = 0; t < c->nrt; ++t) {
+      const RowTile& rt = c->rtiles_h[t];
+      const RepDesc& d = c->reps_h[rt.rep];
+      for (int32_t x = rt.a; x < rt.a + rt.nx; ++x) cell_tile[d.coff + rt.row * d.nc + x] = t;
+    }
+  }
   bool ok = up(c->reps, c->reps_h.data(), sizeof(RepDesc) * nrep) &&
             up(c->tiles, c->tiles_h.data(), sizeof(Tile) * c->ntiles) &&
             up(c->tab, &tab, sizeof(PairTab)) &&
             up(c->cell_rep, cell_rep.data(), sizeof(int32_t) * c->ncells) &&
             up(c->lam, ones.data(), sizeof(double) * nrep) &&
             (!c->staged || up(c->rtiles, c->rtiles_h.data(), sizeof(RowTile) * c->nrt)) &&
+            (!c->staged ||
+             up(c->cell_tile, cell_tile.data(), sizeof(int32_t) * (size_t)c->ncells)) &&
             hipMemset(c->st, 0, sizeof(DevState)) == hipSuccess &&
             hipMemset(c->counts, 0, sizeof(int32_t) * c->ncells) == hipSuccess &&
             hipMemset(c->rebuild, 0, sizeof(int32_t) * nrep) == hipSuccess &&
@@ -805,7 +816,7 @@ md_status md_get_neighbors(md_ctx c, int32_t rep, int32_t* count, int32_t* ids, 
       md_status a_rc = dalloc(c, &tmp, (size_t)rows * c->stride);
       if (a_rc) return a_rc;
       launch_decode_staged(c->stream, c->nrt, c->rtiles, c->reps, c->cell_start, c->stride, rows,
-                           c->nbr16, c->ncount, c->nsplit, tmp);
+                           c->nbr16, c->ncount, tmp);
       src = tmp;
     }
     hipError_t e = hipMemcpy2D(ell.data(), sizeof(uint32_t) * d.n, src + d.off,
@@ -873,7 +884,7 @@ md_status md_autotune(md_ctx c, int32_t reps, md_tune* out) {
   }
   std::vector<std::pair<int32_t, int32_t>> cand;
   if (c->staged)
-    cand = {{1, 2}, {1, 4}, {1, 8}};
+    cand = {{1, 4}, {1, 8}, {2, 2}, {2, 4}, {2, 8}, {4, 2}};
   else
     cand = {{1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 1}, {4, 2}, {8, 1}};
   hipEvent_t e0, e1;

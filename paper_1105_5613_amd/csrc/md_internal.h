@@ -189,25 +189,25 @@ void launch_msd(hipStream_t s, int32_t ntiles, int32_t nrep, const Tile* tiles,
 void launch_rdf(hipStream_t s, const double4* pos, int32_t off, int32_t n, double L, double rmax,
                 int32_t nbins, unsigned long long* hist);
 
-// staged path (stage.h, nlist_staged.hip, force_staged.hip)
+// staged path (stage.h, nlist.hip tile mode, force_staged.hip)
 struct RowTile;
-size_t nlist_staged_lds_bytes(int32_t lcap);
 size_t force_staged_lds_bytes(int32_t lcap);
-void launch_nlist_staged(hipStream_t s, int32_t bt, int32_t nrt, const RowTile* rtiles,
-                         const RepDesc* reps, const int32_t* rebuild, const PairTab* tab,
-                         const int32_t* cell_start, int32_t stride, int32_t cap, int32_t lcap,
-                         const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
-                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr,
-                         int32_t* ncount, uint32_t* nsplit, DevState* st);
+int32_t staged_homes_per_group();
+void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
+                        const RepDesc* reps, const int32_t* rebuild, const PairTab* tab,
+                        const int32_t* cell_start, int32_t stride, int32_t cap,
+                        const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
+                        double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
+                        int32_t* ncount, DevState* st, const int32_t* cell_tile,
+                        const RowTile* rtiles);
 void launch_decode_staged(hipStream_t s, int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
                           const int32_t* cell_start, int32_t stride, int32_t rows,
-                          const uint16_t* nbr, const int32_t* ncount, const uint32_t* nsplit,
-                          uint32_t* out);
-void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t bt, int32_t unroll,
+                          const uint16_t* nbr, const int32_t* ncount, uint32_t* out);
+void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
                          int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
                          const PairTab* tab, const int32_t* cell_start, const double4* pos,
                          double* vel, void* frc, const uint16_t* nbr, const int32_t* ncount,
-                         const uint32_t* nsplit, int32_t stride, int32_t cap, int32_t lcap,
-                         double dt, double* part, DevState* st);
+                         int32_t stride, int32_t cap, int32_t lcap, double dt, double* part,
+                         DevState* st);
 
 }  // namespace mdk

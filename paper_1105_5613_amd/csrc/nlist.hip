@@ -11,7 +11,7 @@
 // List entry: sorted index j (26 bits) | periodic image code (6 bits): two
 // bits per axis holding s in {-1, 0, 1} in two's complement, so an entry
 // without a periodic shift is the plain index.
-#include "md_internal.h"
+#include "stage.h"
 
 #pragma clang fp contract(off)
 
@@ -183,33 +183,71 @@ __global__ __launch_bounds__(kTile) void k_nlist(
 // candidate order.  Copying the new order into the live arrays is done here
 // as well.
 constexpr int kCwGroup = 64;  // home particles per pass: lane h keeps the count of home h
+constexpr int kCwHomes = 4;   // home particles tested per iteration
+constexpr int kCwBuf = 1024;  // list entries staged in LDS per wave (4 KB)
 
-// Test the lane's candidate against home particle ih (wave-uniform) and append
-// the hits to that particle's row; cnt is the particle's running count.
-__device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_t ih,
-                                    uint32_t entry, int32_t cap, int32_t stride,
-                                    uint32_t* __restrict__ nbr) {
+// Append the hits of the lane's candidate for home particle hl of the group
+// (wave-uniform) at that particle's running count cnt.  Rows below rows_lds
+// go to the wave's LDS buffer ([row][home] layout) and reach the list later
+// as whole row segments; rows above it (crowded cells only) are stored
+// straight into the list.
+template <typename E>
+__device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_t hl, int32_t ih,
+                                    uint32_t entry, int32_t cap, int32_t rows_lds, int32_t gn,
+                                    int32_t stride, uint32_t* buf, E* __restrict__ nbr) {
   if (mask) {
     const int32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-    if (hit && cnt + rk < cap) nbr[(size_t)(cnt + rk) * stride + ih] = entry;
+    const int32_t k = cnt + rk;
+    if (hit && k < cap) {
+      if (k < rows_lds)
+        buf[k * gn + hl] = entry;
+      else
+        nbr[(size_t)k * stride + ih] = (E)entry;
+    }
     cnt += (int32_t)__popcll(mask);
   }
   return cnt;
 }
 
+// cut-off threshold of the pair (home species ta, lane's candidate species)
+__device__ inline double pick_thr(int32_t ta, double t0, double t1, double t2, double t3) {
+  return ta == 0 ? t0 : (ta == 1 ? t1 : (ta == 2 ? t2 : t3));
+}
+
+// One wave per home cell (nc >= 3): the lanes take the 64 candidates of one
+// chunk of the cell's packed 27-cell neighbourhood, and the wave walks the
+// home particles (kCwHomes per iteration, positions in scalar registers);
+// hits are compacted with a ballot.  The first kCwBuf / (homes) rows of the
+// cell's lists are assembled in LDS and written out row by row (one
+// contiguous store per row instead of scattered single entries); the LDS
+// buffer is kept small because occupancy matters more here than write
+// combining.
+//
+// TILE = false: entries are sorted index | image code (uint32, gather path).
+// TILE = true: entries are the partner's LDS slot in the staged neighbourhood
+// of the row tile holding the home cell (stage.h) | species << 14 (uint16,
+// staged path); the slot of a candidate is its piece's first slot in that
+// layout plus its offset inside the piece.
+template <int HPI, int BUF, bool TILE>
 __global__ __launch_bounds__(256) void k_nlist_cells(
     int32_t ncells, const int32_t* __restrict__ cell_rep, const RepDesc* __restrict__ reps,
     const int32_t* __restrict__ rebuild, const PairTab* __restrict__ tab,
     const int32_t* __restrict__ cell_start, int32_t stride, int32_t cap,
     const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
     const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
-    int32_t* __restrict__ id, double* __restrict__ xref, uint32_t* __restrict__ nbr,
-    int32_t* __restrict__ ncount, DevState* st, float4* __restrict__ pos16) {
+    int32_t* __restrict__ id, double* __restrict__ xref,
+    typename std::conditional<TILE, uint16_t, uint32_t>::type* __restrict__ nbr,
+    int32_t* __restrict__ ncount, DevState* st, float4* __restrict__ pos16,
+    const int32_t* __restrict__ cell_tile, const RowTile* __restrict__ rtiles) {
+  using E = typename std::conditional<TILE, uint16_t, uint32_t>::type;
   __shared__ double s_thr[16];
   __shared__ int32_t s_pre[4][28];    // first packed candidate of piece p
   __shared__ int32_t s_k0[4][27];     // first sorted index of piece p
   __shared__ int32_t s_code[4][27];   // image code of piece p (shift -1/0/1 per axis)
+  __shared__ int32_t s_l0[4][27];     // TILE: first LDS slot of piece p in the tile layout
+  __shared__ int32_t s_rowsz[4][9];   // TILE: slots of tile row q
+  extern __shared__ uint32_t s_list[];  // [4][kCwBuf]
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -223,6 +261,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   const int32_t lc = c - R.coff;
   const int32_t qx = lc % nc, qy = (lc / nc) % nc, qz = lc / (nc * nc);
   const int32_t h0 = cell_start[c], nh = cell_start[c + 1] - h0;
+  uint32_t* buf = s_list + w * BUF;
 
   // pieces: lane q < 9 builds neighbour row q (dz = q/3 - 1, dy = q%3 - 1)
   if (lane < 9) {
@@ -245,6 +284,20 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
     s_pre[w][p] = nl;  // lengths for now
     s_pre[w][p + 1] = nm;
     s_pre[w][p + 2] = nr;
+    if constexpr (TILE) {
+      // the tile's row q: left piece (logical cell a-1 < 0), main cells, right
+      // piece (logical cell a+nx >= nc); offsets of this cell's pieces in it
+      const RowTile T = rtiles[cell_tile[c]];
+      const int32_t tlo = T.a - 1, thi = T.a + T.nx;
+      const int32_t mlo = tlo < 0 ? 0 : tlo, mhi = thi >= nc ? nc - 1 : thi;
+      const int32_t lsz = tlo < 0 ? cell_start[rowbase + nc] - cell_start[rowbase + nc - 1] : 0;
+      const int32_t msz = cell_start[rowbase + mhi + 1] - cell_start[rowbase + mlo];
+      const int32_t rsz = thi >= nc ? cell_start[rowbase + 1] - cell_start[rowbase] : 0;
+      s_rowsz[w][lane] = lsz + msz + rsz;
+      s_l0[w][p] = 0;
+      s_l0[w][p + 1] = lsz + (cell_start[rowbase + lo] - cell_start[rowbase + mlo]);
+      s_l0[w][p + 2] = lsz + msz;
+    }
   }
   __builtin_amdgcn_wave_barrier();
   if (lane == 0) {
@@ -255,6 +308,14 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
       acc += len;
     }
     s_pre[w][27] = acc;
+    if constexpr (TILE) {
+      int32_t ro = 0;
+      for (int q = 0; q < 9; ++q) {
+        for (int u = 0; u < 3; ++u) s_l0[w][3 * q + u] += ro;
+        ro += s_rowsz[w][q];
+      }
+      if (ro > kMaxStaged) atomicOr(&st->err, kErrOverflow);
+    }
   }
   __builtin_amdgcn_wave_barrier();
   const int32_t ncand = s_pre[w][27];
@@ -262,13 +323,16 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   for (int32_t g0 = 0; g0 < nh; g0 += kCwGroup) {
     const int32_t gn = nh - g0 < kCwGroup ? nh - g0 : kCwGroup;
     const int32_t gbase = h0 + g0;
+    const int32_t rows_lds = BUF / gn;
     int32_t cntv = 0;  // lane h: neighbours found so far for home gbase + h
     for (int32_t base = 0; base < ncand; base += 64) {
       const int32_t v = base + lane;
       const bool valid = v < ncand;
+      // piece of candidate v: the last p with s_pre[p] <= v
       int p = 0;
-      for (int q = 1; q < 27; ++q)
-        if (s_pre[w][q] <= v) p = q;
+#pragma unroll
+      for (int step = 16; step >= 1; step >>= 1)
+        if (p + step <= 26 && s_pre[w][p + step] <= v) p += step;
       const int32_t k = valid ? s_k0[w][p] + (v - s_pre[w][p]) : h0;
       const uint32_t code = (uint32_t)s_code[w][p];
       const double4 q = pos_tmp[k];
@@ -277,38 +341,46 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
       const double sy = (double)(((int32_t)(code << 2)) >> 30) * R.L;
       const double sz = (double)(((int32_t)code) >> 30) * R.L;
       const double xs = q.x + sx, ys = q.y + sy, zs = q.z + sz;
-      const double* thr = &s_thr[(int32_t)q.w];  // thr[4 * ti] is the pair (ti, tj)
-      const uint32_t entry = (uint32_t)k | code;
+      const int32_t tj = (int32_t)q.w;  // thr[4 ta + tj] is the pair (ta, tj)
+      const double t0 = s_thr[tj], t1 = s_thr[4 + tj], t2 = s_thr[8 + tj], t3 = s_thr[12 + tj];
+      uint32_t entry;
+      if constexpr (TILE)
+        entry = (uint32_t)((s_l0[w][p] + (v - s_pre[w][p])) & 0x3fff) | ((uint32_t)tj << 14);
+      else
+        entry = (uint32_t)k | code;
       int32_t h = 0;
-      // two home particles per iteration (wave-uniform, scalar loads)
-      for (; h + 2 <= gn; h += 2) {
-        const int32_t ia = __builtin_amdgcn_readfirstlane(gbase + h);
-        const int32_t ib = ia + 1;
-        const double4 pa = pos_tmp[ia];
-        const double4 pb = pos_tmp[ib];
-        const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
-        const double bx = xs - pb.x, by = ys - pb.y, bz = zs - pb.z;
-        const double ra = (ax * ax + ay * ay) + az * az;
-        const double rb = (bx * bx + by * by) + bz * bz;
-        const bool hita = (int)valid & (int)(k != ia) & (int)(ra < thr[4 * (int32_t)pa.w]);
-        const bool hitb = (int)valid & (int)(k != ib) & (int)(rb < thr[4 * (int32_t)pb.w]);
-        const uint64_t ma = __ballot(hita), mb = __ballot(hitb);
-        int32_t ca = __builtin_amdgcn_readlane(cntv, h);
-        int32_t cb = __builtin_amdgcn_readlane(cntv, h + 1);
-        ca = cw_append(ma, hita, ca, ia, entry, cap, stride, nbr);
-        cb = cw_append(mb, hitb, cb, ib, entry, cap, stride, nbr);
-        cntv = lane == h ? ca : cntv;
-        cntv = lane == h + 1 ? cb : cntv;
+      // HPI home particles per iteration (wave-uniform, scalar loads)
+      for (; h + HPI <= gn; h += HPI) {
+        const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
+        bool hit[HPI];
+        uint64_t m[HPI];
+#pragma unroll
+        for (int u = 0; u < HPI; ++u) {
+          const double4 pa = pos_tmp[i0 + u];
+          const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
+          const double ra = (ax * ax + ay * ay) + az * az;
+          const double tha = pick_thr((int32_t)pa.w, t0, t1, t2, t3);
+          hit[u] = (int)valid & (int)(k != i0 + u) & (int)(ra < tha);
+          m[u] = __ballot(hit[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < HPI; ++u) {
+          int32_t cu = __builtin_amdgcn_readlane(cntv, h + u);
+          cu = cw_append(m[u], hit[u], cu, h + u, i0 + u, entry, cap, rows_lds, gn, stride, buf,
+                         nbr);
+          cntv = lane == h + u ? cu : cntv;
+        }
       }
-      if (h < gn) {
+      for (; h < gn; ++h) {
         const int32_t ia = __builtin_amdgcn_readfirstlane(gbase + h);
         const double4 pa = pos_tmp[ia];
         const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
         const double ra = (ax * ax + ay * ay) + az * az;
-        const bool hita = (int)valid & (int)(k != ia) & (int)(ra < thr[4 * (int32_t)pa.w]);
+        const double tha = pick_thr((int32_t)pa.w, t0, t1, t2, t3);
+        const bool hita = (int)valid & (int)(k != ia) & (int)(ra < tha);
         const uint64_t ma = __ballot(hita);
         int32_t ca = __builtin_amdgcn_readlane(cntv, h);
-        ca = cw_append(ma, hita, ca, ia, entry, cap, stride, nbr);
+        ca = cw_append(ma, hita, ca, h, ia, entry, cap, rows_lds, gn, stride, buf, nbr);
         cntv = lane == h ? ca : cntv;
       }
     }
@@ -316,6 +388,24 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
       ncount[gbase + lane] = cntv;
       if (cntv > cap) atomicOr(&st->err, kErrOverflow);
     }
+    if (BUF == 0) continue;
+    // write the staged rows: row k of the group is gn consecutive entries
+    int32_t mx = lane < gn ? cntv : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d, 64));
+    const int32_t rows = min(min(mx, cap), rows_lds);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int32_t per = 64 / gn;  // rows per store
+    const int32_t lr = lane / gn, lh = lane - lr * gn;
+    if (lr < per)
+      for (int32_t kk = lr; kk < rows; kk += per)
+        nbr[(size_t)kk * stride + gbase + lh] = (E)buf[kk * gn + lh];
+    // the next group reuses the buffer
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   // the new cell order becomes the live state
   for (int32_t h = lane; h < nh; h += 64) {
@@ -343,14 +433,26 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   int32_t* ncount, DevState* st, int32_t ncells, const int32_t* cell_rep,
                   int32_t any_single, int32_t any_multi, float4* pos16) {
   if (any_multi)
-    k_nlist_cells<<<(ncells + 3) / 4, 256, 0, s>>>(ncells, cell_rep, reps, rebuild, tab,
-                                                   cell_start, stride, cap, pos_tmp, vel_tmp,
-                                                   id_tmp, pos, vel, id, xref, nbr, ncount, st,
-                                                   pos16);
+    k_nlist_cells<kCwHomes, kCwBuf, false>
+        <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(
+            ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp,
+            id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr);
   if (any_single)
     k_nlist<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, tab, ntypes, cell_start, stride, cap,
                                      pos_tmp, vel_tmp, id_tmp, pos, vel, id, xref, nbr, ncount,
                                      st, 1, pos16);
+}
+
+void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
+                        const RepDesc* reps, const int32_t* rebuild, const PairTab* tab,
+                        const int32_t* cell_start, int32_t stride, int32_t cap,
+                        const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
+                        double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
+                        int32_t* ncount, DevState* st, const int32_t* cell_tile,
+                        const RowTile* rtiles) {
+  k_nlist_cells<kCwHomes, kCwBuf, true><<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(
+      ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, id_tmp, pos,
+      vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles);
 }
 
 }  // namespace mdk

@@ -1,5 +1,6 @@
 // stage.h -- row tiles and their LDS-staged neighbourhoods (device helpers
-// shared by the staged neighbour search, force and list-decode kernels).
+// shared by the staged force kernel, the staged neighbour-list entries and
+// their decode).
 //
 // A row tile is a run of home cells [a, a + nx) of one x-row (cy, cz) of a
 // replica's cell grid.  With cells of side >= cutoff + skin, every partner of
@@ -7,20 +8,17 @@
 // along x, in the logical cells a-1 .. a+nx.  Cells are stored in z-major
 // order, so each neighbour row contributes up to three contiguous particle
 // ranges ("pieces"): the main range and, where the row wraps around the
-// periodic box, one cell on either side.  Each piece is staged into LDS with
-// its periodic shift s*L already added, in FP64, i.e. exactly the value
-// x_j + s*L that the cut-off test uses.  Logical cells stay contiguous in LDS,
-// so the candidates of a home particle in cell cx are, per neighbour row, the
-// single LDS range [start(cx-1), start(cx+2)).
+// periodic box, one cell on either side.  All 27 pieces are staged into LDS
+// once per block, with their periodic shift s*L already added, in FP64, i.e.
+// exactly the value x_j + s*L that the cut-off test uses; rows follow each
+// other in the order (dz, dy) = (-1,-1), (-1,0), ... (1,1) and inside a row
+// the left piece, the main range and the right piece.  Logical cells stay
+// contiguous in LDS, so the partners of a home particle in cell cx are, per
+// neighbour row, in the single slot range [start(cx-1), start(cx+2)).
 //
-// The neighbourhood is staged in three passes, one per z-offset (three
-// neighbour rows each), which keeps the LDS footprint of a block small enough
-// for high occupancy.  A home particle's list holds the entries of pass 0,
-// then pass 1, then pass 2 (the neighbour search visits rows in that order);
-// nsplit[i] = n0 | n1 << 16 records the first two pass lengths.  An entry is
-// the slot relative to its pass (14 bits) | species << 14.  A pass whose size
-// exceeds the LDS capacity keeps working: slots at or above the capacity are
-// fetched from global memory through the piece table ("virtual" slots).
+// A staged list entry is the LDS slot (14 bits) | species << 14.  Slots at or
+// above the LDS capacity of a launch are fetched from global memory through
+// the piece table ("virtual" slots), so an unusually dense tile still works.
 #pragma once
 #include "md_internal.h"
 
@@ -130,46 +128,37 @@ __device__ inline void build_layout(StageLayout& S, const RowTile& T, const RepD
   __syncthreads();
 }
 
+// Piece of slot v: the last p with pc_l[p] <= v (binary lifting; empty
+// pieces never match because the next piece starts at the same slot).
 __device__ inline int piece_of(const StageLayout& S, int32_t v) {
   int p = 0;
-#pragma unroll 1
-  for (int q = 1; q < kPieces; ++q)
-    if (S.pc_l[q] <= v) p = q;
+#pragma unroll
+  for (int step = 16; step >= 1; step >>= 1)
+    if (p + step < kPieces && S.pc_l[p + step] <= v) p += step;
   return p;
 }
 
 // Staged coordinates of slot v straight from global memory (virtual slots).
+// A slot past the layout (only after a reported overflow) is clamped so the
+// read stays inside the tile's pieces.
 __device__ inline double4 fetch_slot(const StageLayout& S, const double4* __restrict__ pos,
                                      int32_t v) {
+  v = v < S.total ? v : S.total - 1;
   const int p = piece_of(S, v);
   const double4 q = pos[S.pc_g[p] + (v - S.pc_l[p])];
   return make_double4(q.x + S.pc_sx[p], q.y + S.pc_sy[p], q.z + S.pc_sz[p], q.w);
 }
 
-__device__ inline int32_t pass_base(const StageLayout& S, int pass) { return S.pc_l[9 * pass]; }
-__device__ inline int32_t pass_size(const StageLayout& S, int pass) {
-  return S.pc_l[9 * pass + 9] - S.pc_l[9 * pass];
-}
-
-// Copy the rows of one pass into LDS (slots below cap, relative to the pass
-// base); ends with a barrier.
-template <bool TYPES>
-__device__ inline void stage(const StageLayout& S, int pass, const double4* __restrict__ pos,
-                             int32_t cap, double* xs, double* ys, double* zs, uint8_t* ts) {
-  const int32_t base = pass_base(S, pass);
-  for (int p = 9 * pass; p < 9 * pass + 9; ++p) {
-    const int32_t l0 = S.pc_l[p] - base, n = S.pc_l[p + 1] - S.pc_l[p], g0 = S.pc_g[p];
-    const double sx = S.pc_sx[p], sy = S.pc_sy[p], sz = S.pc_sz[p];
-    for (int32_t q = threadIdx.x; q < n; q += blockDim.x) {
-      const int32_t v = l0 + q;
-      if (v < cap) {
-        const double4 r = pos[g0 + q];
-        xs[v] = r.x + sx;
-        ys[v] = r.y + sy;
-        zs[v] = r.z + sz;
-        if (TYPES) ts[v] = (uint8_t)(int32_t)r.w;
-      }
-    }
+// Copy all pieces into LDS (slots below cap) as (x, y) pairs and z values;
+// ends with a barrier.
+__device__ inline void stage_all(const StageLayout& S, const double4* __restrict__ pos,
+                                 int32_t cap, double2* xy, double* zz) {
+  const int32_t m = S.total < cap ? S.total : cap;
+  for (int32_t v = threadIdx.x; v < m; v += blockDim.x) {
+    const int p = piece_of(S, v);
+    const double4 r = pos[S.pc_g[p] + (v - S.pc_l[p])];
+    xy[v] = make_double2(r.x + S.pc_sx[p], r.y + S.pc_sy[p]);
+    zz[v] = r.z + S.pc_sz[p];
   }
   __syncthreads();
 }

@@ -42,8 +42,7 @@ class Params(C.Structure):
                 ("rc", C.c_double * 16), ("mass", C.c_double * 4), ("skin", C.c_double),
                 ("dt", C.c_double), ("max_neighbors", C.c_int32), ("graph_steps", C.c_int32),
                 ("tpp", C.c_int32), ("unroll", C.c_int32),
-                ("path", C.c_int32), ("tile_threads", C.c_int32), ("tile_cells", C.c_int32),
-                ("stage_slots", C.c_int32)]
+                ("path", C.c_int32), ("tile_cells", C.c_int32), ("stage_slots", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -111,8 +110,8 @@ def lib():
 
 def make_params(eps, sig, rc, mass, *, skin=0.3, dt=0.005, precision=MD_FP64,
                 potential=MD_POT_LJ, trunc=MD_TRUNC_SHIFTED_FORCE, max_neighbors=0,
-                graph_steps=0, tpp=0, unroll=0, path=MD_PATH_AUTO, tile_threads=0,
-                tile_cells=0, stage_slots=0) -> Params:
+                graph_steps=0, tpp=0, unroll=0, path=MD_PATH_AUTO, tile_cells=0,
+                stage_slots=0) -> Params:
     p = Params()
     nt = len(eps)
     p.ntypes = nt
@@ -132,7 +131,6 @@ def make_params(eps, sig, rc, mass, *, skin=0.3, dt=0.005, precision=MD_FP64,
     p.tpp = int(tpp)
     p.unroll = int(unroll)
     p.path = int(path)
-    p.tile_threads = int(tile_threads)
     p.tile_cells = int(tile_cells)
     p.stage_slots = int(stage_slots)
     return p

@@ -1,5 +1,5 @@
 """Autotuner for choices that need a fresh context: kernel path (gather or
-staged), list skin, staged tile threads.  Each candidate runs a short trial
+staged), list skin, staged tile length (cells per row tile).  Each candidate runs a short trial
 from the caller's state in its own context (the caller's context is never
 touched); inside each trial md_autotune picks the force-kernel variant
 (lanes per particle, unroll).  The fastest candidate wins.
@@ -49,7 +49,7 @@ def _min_cells(L, params: md.Params, skin: float) -> int:
 
 def autotune(params: md.Params, n, L, x, v, types, *, T0=None, steps: int = 60,
              warmup: int = 20, skins=None, paths=(md.MD_PATH_GATHER, md.MD_PATH_STAGED),
-             tile_threads=(128, 256), cache_path: str | None = DEFAULT_CACHE,
+             tile_cells=(0,), cache_path: str | None = DEFAULT_CACHE,
              use_cache: bool = True):
     """Return (tuned Params, report).  n, L: per-replica sizes and box sides;
     x, v, types: the state to trial on (device or host arrays)."""
@@ -69,8 +69,8 @@ def autotune(params: md.Params, n, L, x, v, types, *, T0=None, steps: int = 60,
             if path == md.MD_PATH_STAGED:
                 if _min_cells(L, params, skin) < 3:
                     continue
-                for bt in tile_threads:
-                    cands.append(dict(path=path, skin=float(skin), tile_threads=bt))
+                for tc in tile_cells:
+                    cands.append(dict(path=path, skin=float(skin), tile_cells=int(tc)))
             else:
                 cands.append(dict(path=path, skin=float(skin)))
     trials = []

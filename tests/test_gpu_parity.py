@@ -59,7 +59,7 @@ PATHS = {"gather": dict(path=1), "staged": dict(path=2)}
     (32000, 8, dict(path=2, tile_cells=1)),                  # one home cell per tile
     (32000, 9, dict(path=2, tile_cells=64)),                 # whole rows: both wrap pieces
     (32000, 10, dict(path=2, stage_slots=256)),              # most slots from global memory
-    (13500, 11, dict(path=2, tile_threads=128, unroll=8)),
+    (13500, 11, dict(path=2, tpp=1, unroll=8)),
 ], ids=["4k-gather", "4k-staged", "32k-gather", "32k-staged", "500-onecell", "32k-cell1",
         "32k-row", "32k-slots256", "13.5k-bt128"])
 def test_cells_lists_forces_fp64(torch_cuda, n, seed, kw):
