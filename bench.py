@@ -233,14 +233,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--forms", default="fp64,mixed,batched")
+    ap.add_argument("--forms", default="fp64,mixed,large,batched")
     ap.add_argument("--profile-every", type=int, default=4,
                     help="bracket the force launch of every k-th timed step with hipEvents")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--replicas", type=int, default=256)
-    ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--batched-steps", type=int, default=2000)
+    ap.add_argument("--large-n", type=int, default=67108864)
+    ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--serial-steps", type=int, default=50)
     ap.add_argument("--graph-steps", type=int, default=100,
                     help="steps per captured hipGraph in the batched form (0: direct launches)")
@@ -296,6 +298,25 @@ def main():
                         "tuned": r["tuned"]}
     if "fp64" in res and "mixed" in res:
         forms_out["speedup_mixed_vs_fp64"] = round(res["mixed"]["rate"] / res["fp64"]["rate"], 4)
+    if "large" in forms:
+        nl = args.large_n
+        log(f"generating inputs n={nl}")
+        big = initconf.fcc_system(nl, seed=3, temperature=2.0)
+        log(f"timing the large mixed form: {args.large_steps} steps after 20 warmup")
+        rl = run_single(torch, 1, big, args.large_steps, 20, args.profile_every)
+        del big
+        bl = force_bytes_per_particle(rl["nbar"], True)
+        ach = nl * bl / (max(rl["force_ms_avg"], 1e-12) * 1e-3) / 1e9
+        log(f"  large mixed: {rl['rate']:.4e} particle-steps/s, {rl['ms_per_step']:.3f} ms/step, "
+            f"force {rl['force_ms_avg']:.3f} ms")
+        forms_out["large_mixed"] = {
+            "workload": f"lj{nl}: {nl}-particle binary LJ mixture, mixed precision, T=2.0 NVE, "
+                        "dt 0.005, skin 0.3",
+            "value": round(rl["rate"], 1), "ms_per_step": round(rl["ms_per_step"], 4),
+            "force_ms_avg": round(rl["force_ms_avg"], 4), "force_achieved_gbs": round(ach, 1),
+            "force_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+            "mean_list_length": round(rl["nbar"], 3), "rebuilds": rl["rebuilds"],
+            "tuned": rl["tuned"]}
     if "batched" in forms:
         log(f"timing batched replicas: {args.replicas} boxes, {args.batched_steps} steps")
         systems, temps = replica_inputs(args.replicas)

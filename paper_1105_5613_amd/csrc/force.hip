@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kTile) void k_force(
   if (active) {
     int32_t n = ncount[i];
     n = n < cap ? n : cap;
-    const uint32_t* row = nbr + i;
+    const uint32_t* row = nbr + list_base(i, cap);
     // entries are fetched one chunk of U ahead; slots past n point at the
     // particle itself and are masked out
     const uint32_t self = (uint32_t)i;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kTile) void k_force(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t k = lane_p + u * TPP;
-      e[u] = k < n ? row[(size_t)k * stride] : self;
+      e[u] = k < n ? row[(size_t)k * kSlice] : self;
     }
     if constexpr (MIXED) {
       // 16-byte cell-relative records (see make_rec16)
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kTile) void k_force(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t k = k0 + (U + u) * TPP;
-          en[u] = k < n ? row[(size_t)k * stride] : self;
+          en[u] = k < n ? row[(size_t)k * kSlice] : self;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kTile) void k_force(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t k = k0 + (U + u) * TPP;
-          en[u] = k < n ? row[(size_t)k * stride] : self;
+          en[u] = k < n ? row[(size_t)k * kSlice] : self;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kStageHomes* TPP) void k_force_staged(
     const int32_t ti = (int32_t)p.w;
     int32_t n = mine ? ncount[i] : 0;
     n = n < cap ? n : cap;
-    const uint16_t* row = nbr + i;
+    const uint16_t* row = nbr + list_base(i, cap);
     T fx = 0, fy = 0, fz = 0, pe_i = 0, w_i = 0;
     // list slots of the next chunk are loaded ahead; slots past n repeat
     // slot 0 and are masked out
@@ -113,14 +113,14 @@ __global__ __launch_bounds__(kStageHomes* TPP) void k_force_staged(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t k = lane_p + u * TPP;
-      e[u] = k < n ? (uint32_t)row[(size_t)k * stride] : 0u;
+      e[u] = k < n ? (uint32_t)row[(size_t)k * kSlice] : 0u;
     }
     for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
       uint32_t en[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int32_t k = k0 + (U + u) * TPP;
-        en[u] = k < n ? (uint32_t)row[(size_t)k * stride] : 0u;
+        en[u] = k < n ? (uint32_t)row[(size_t)k * kSlice] : 0u;
       }
       double qx[U], qy[U], qz[U];
 #pragma unroll
@@ -206,9 +206,8 @@ __global__ __launch_bounds__(kStageHomes* TPP) void k_force_staged(
 // Staged entries -> sorted particle indices (parity hook only).
 __global__ __launch_bounds__(256) void k_decode_staged(
     const RowTile* __restrict__ rtiles, const RepDesc* __restrict__ reps,
-    const int32_t* __restrict__ cell_start, int32_t stride, int32_t rows,
-    const uint16_t* __restrict__ nbr, const int32_t* __restrict__ ncount,
-    uint32_t* __restrict__ out) {
+    const int32_t* __restrict__ cell_start, int32_t cap, const uint16_t* __restrict__ nbr,
+    const int32_t* __restrict__ ncount, uint32_t* __restrict__ out) {
   __shared__ StageLayout S;
   const RowTile T = rtiles[blockIdx.x];
   const RepDesc R = reps[T.rep];
@@ -217,12 +216,13 @@ __global__ __launch_bounds__(256) void k_decode_staged(
   for (int32_t li = threadIdx.x; li < nh; li += blockDim.x) {
     const int32_t i = S.home0 + li;
     int32_t n = ncount[i];
-    n = n < rows ? n : rows;
+    n = n < cap ? n : cap;
+    const size_t b = list_base(i, cap);
     for (int32_t k = 0; k < n; ++k) {
-      int32_t v = nbr[(size_t)k * stride + i] & 0x3fff;
+      int32_t v = nbr[b + (size_t)k * kSlice] & 0x3fff;
       v = v < S.total ? v : S.total - 1;  // only after a reported overflow
       const int p = piece_of(S, v);
-      out[(size_t)k * stride + i] = (uint32_t)(S.pc_g[p] + (v - S.pc_l[p]));
+      out[b + (size_t)k * kSlice] = (uint32_t)(S.pc_g[p] + (v - S.pc_l[p]));
     }
   }
 }
@@ -267,9 +267,9 @@ void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp
 }
 
 void launch_decode_staged(hipStream_t s, int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
-                          const int32_t* cell_start, int32_t stride, int32_t rows,
-                          const uint16_t* nbr, const int32_t* ncount, uint32_t* out) {
-  k_decode_staged<<<nrt, 256, 0, s>>>(rtiles, reps, cell_start, stride, rows, nbr, ncount, out);
+                          const int32_t* cell_start, int32_t cap, const uint16_t* nbr,
+                          const int32_t* ncount, uint32_t* out) {
+  k_decode_staged<<<nrt, 256, 0, s>>>(rtiles, reps, cell_start, cap, nbr, ncount, out);
 }
 
 }  // namespace mdk

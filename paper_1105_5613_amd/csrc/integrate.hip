@@ -89,6 +89,7 @@ constexpr int kRedThreads = 1024;
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restrict__ reps,
                                                         const double* __restrict__ part,
                                                         const double* __restrict__ dmax,
+                                                        const double* __restrict__ part2,
                                                         int32_t step, ThermoArgs ta,
                                                         int64_t* __restrict__ kcall,
                                                         double* __restrict__ lam,
@@ -98,14 +99,20 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
   const int32_t r = blockIdx.x;
   const RepDesc R = reps[r];
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
-  const int32_t b0 = R.fb0, b1 = R.fb1;
-  for (int32_t b = b0 + threadIdx.x; b < b1; b += kRedThreads)
-    for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
+  double m = 0.0;  // largest squared displacement of this step's drift
+  if (part2) {
+    for (int32_t b = R.cb0 + threadIdx.x; b < R.cb1; b += kRedThreads) {
+      for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part2[4 * (size_t)b + k]);
+      m = fmax(m, part2[4 * (size_t)b + 3]);
+    }
+  } else {
+    for (int32_t b = R.fb0 + threadIdx.x; b < R.fb1; b += kRedThreads)
+      for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
+    if (step)
+      for (int32_t b = R.tile0 + threadIdx.x; b < R.tile1; b += kRedThreads)
+        m = fmax(m, dmax[b]);
+  }
   for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
-  // largest squared displacement of this step's drift (tile maxima)
-  double m = 0.0;
-  if (step)
-    for (int32_t b = R.tile0 + threadIdx.x; b < R.tile1; b += kRedThreads) m = fmax(m, dmax[b]);
   red[3][threadIdx.x] = m;
   __syncthreads();
   for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
@@ -158,6 +165,34 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
       if (idx >= 0 && idx < ta.nlog) ta.log[idx * gridDim.x + r] = o;
     }
   }
+}
+
+// First level of the two-level reduction: one block per chunk, fixed order.
+constexpr int kChunkThreads = 256;
+__global__ __launch_bounds__(kChunkThreads) void k_reduce_chunks(const RedChunk* __restrict__ ch,
+                                                                 const double* __restrict__ part,
+                                                                 const double* __restrict__ dmax,
+                                                                 int32_t step,
+                                                                 double* __restrict__ part2) {
+  __shared__ double red[4][kChunkThreads];
+  const RedChunk C = ch[blockIdx.x];
+  double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
+  for (int32_t b = C.b0 + threadIdx.x; b < C.b1; b += kChunkThreads)
+    for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
+  double m = 0.0;
+  if (step)
+    for (int32_t t = C.t0 + threadIdx.x; t < C.t1; t += kChunkThreads) m = fmax(m, dmax[t]);
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
+  red[3][threadIdx.x] = m;
+  __syncthreads();
+  for (int h = kChunkThreads / 2; h >= 1; h >>= 1) {
+    if (threadIdx.x < h) {
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part2[4 * (size_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
 __global__ void k_after_build(int32_t nrep, int32_t* rebuild, md_obs* obs, DevState* st) {
@@ -217,9 +252,15 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
 }
 
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
-                   const double* dmax, int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
-                   int32_t* rebuild, md_obs* obs, DevState* st) {
-  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, dmax, step, ta, kcall, lam, rebuild, obs, st);
+                   const double* dmax, const double* part2, int32_t step, ThermoArgs ta,
+                   int64_t* kcall, double* lam, int32_t* rebuild, md_obs* obs, DevState* st) {
+  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, dmax, part2, step, ta, kcall, lam, rebuild,
+                                        obs, st);
+}
+
+void launch_reduce_chunks(hipStream_t s, int32_t nchunks, const RedChunk* ch, const double* part,
+                          const double* dmax, int32_t step, double* part2) {
+  k_reduce_chunks<<<nchunks, kChunkThreads, 0, s>>>(ch, part, dmax, step, part2);
 }
 
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* obs,

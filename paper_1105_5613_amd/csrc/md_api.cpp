@@ -45,6 +45,11 @@ struct md_ctx_s {
   double* part = nullptr;
   int32_t* rebuild = nullptr;
   double* dmax = nullptr;   // [ntiles] per-tile max of the last drift
+  // two-level reduction of the force partials (large replicas only)
+  std::vector<RedChunk> chunks_h;
+  RedChunk* chunks = nullptr;
+  int32_t nchunks = 0, max_chunks = 0;
+  double* part2 = nullptr;
   md_obs* obs = nullptr;
   int64_t* kcall = nullptr;
   double* lam = nullptr;
@@ -222,11 +227,11 @@ md_status grow_capacity(md_ctx c) {
   if (c->staged) {
     dfree(c, c->nbr16);
     c->nbr16 = nullptr;
-    rc = dalloc(c, &c->nbr16, (size_t)cap * c->stride);
+    rc = dalloc(c, &c->nbr16, list_elems(c->ntot, cap));
   } else {
     dfree(c, c->nbr);
     c->nbr = nullptr;
-    rc = dalloc(c, &c->nbr, (size_t)cap * c->stride);
+    rc = dalloc(c, &c->nbr, list_elems(c->ntot, cap));
   }
   if (rc) return rc;
   c->cap = cap;
@@ -258,10 +263,45 @@ ThermoArgs no_thermo() {
   return t;
 }
 
+void launch_reductions(md_ctx c, hipStream_t s, int32_t step, const ThermoArgs& ta) {
+  if (c->nchunks) launch_reduce_chunks(s, c->nchunks, c->chunks, c->part, c->dmax, step, c->part2);
+  launch_reduce(s, c->nrep, c->reps, c->part, c->dmax, c->nchunks ? c->part2 : nullptr, step, ta,
+                c->kcall, c->lam, c->rebuild, c->obs, c->st);
+}
+
+// Split every replica's partial blocks [fb0, fb1) (and drift tiles) into
+// chunks of about kRedChunk when some replica has more than 4 chunks' worth;
+// otherwise the per-replica pass reads the partials directly.  Host side
+// only: the caller uploads reps and chunks.
+void plan_chunks(md_ctx c) {
+  int32_t most = 0;
+  for (const RepDesc& d : c->reps_h) most = std::max(most, d.fb1 - d.fb0);
+  c->chunks_h.clear();
+  if (most <= 4 * kRedChunk) {
+    c->nchunks = 0;
+    for (RepDesc& d : c->reps_h) d.cb0 = d.cb1 = 0;
+    return;
+  }
+  for (RepDesc& d : c->reps_h) {
+    const int64_t nb = d.fb1 - d.fb0, nt = d.tile1 - d.tile0;
+    const int64_t nch = std::max<int64_t>(1, (nb + kRedChunk - 1) / kRedChunk);
+    d.cb0 = (int32_t)c->chunks_h.size();
+    for (int64_t j = 0; j < nch; ++j) {
+      RedChunk ch;
+      ch.b0 = d.fb0 + (int32_t)(nb * j / nch);
+      ch.b1 = d.fb0 + (int32_t)(nb * (j + 1) / nch);
+      ch.t0 = d.tile0 + (int32_t)(nt * j / nch);
+      ch.t1 = d.tile0 + (int32_t)(nt * (j + 1) / nch);
+      c->chunks_h.push_back(ch);
+    }
+    d.cb1 = (int32_t)c->chunks_h.size();
+  }
+  c->nchunks = (int32_t)c->chunks_h.size();
+}
+
 void launch_forces0(md_ctx c) {
   launch_forces(c, 0, c->stream);
-  launch_reduce(c->stream, c->nrep, c->reps, c->part, c->dmax, 0, no_thermo(), c->kcall, c->lam,
-                c->rebuild, c->obs, c->st);
+  launch_reductions(c, c->stream, 0, no_thermo());
 }
 
 
@@ -281,8 +321,7 @@ md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t th
     HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
     c->ev_used += 2;
   }
-  launch_reduce(s, c->nrep, c->reps, c->part, c->dmax, 1, ta, c->kcall, c->lam, c->rebuild,
-                c->obs, c->st);
+  launch_reductions(c, s, 1, ta);
   return MD_OK;
 }
 
@@ -563,16 +602,22 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
   ALLOC(c->id_tmp, N);
   ALLOC(c->img, 3 * N);
   if (c->staged) {
-    ALLOC(c->nbr16, (size_t)c->cap * S);
+    ALLOC(c->nbr16, list_elems(c->ntot, c->cap));
     ALLOC(c->cell_tile, (size_t)c->ncells);
     ALLOC(c->rtiles, (size_t)c->nrt);
   } else {
-    ALLOC(c->nbr, (size_t)c->cap * S);
+    ALLOC(c->nbr, list_elems(c->ntot, c->cap));
   }
   ALLOC(c->ncount, N);
   ALLOC(c->part, 4 * std::max((size_t)c->ntiles * 8, (size_t)c->nrt));
   ALLOC(c->rebuild, (size_t)nrep);
   ALLOC(c->dmax, (size_t)c->ntiles);
+  plan_chunks(c);
+  c->max_chunks =
+      (int32_t)((std::max((size_t)c->ntiles * 8, (size_t)c->nrt) + kRedChunk - 1) / kRedChunk) +
+      nrep;
+  ALLOC(c->chunks, (size_t)c->max_chunks);
+  ALLOC(c->part2, 4 * (size_t)c->max_chunks);
   ALLOC(c->obs, (size_t)nrep);
   ALLOC(c->kcall, (size_t)nrep);
   ALLOC(c->lam, (size_t)nrep);
@@ -597,6 +642,7 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
             up(c->cell_rep, cell_rep.data(), sizeof(int32_t) * c->ncells) &&
             up(c->lam, ones.data(), sizeof(double) * nrep) &&
             (!c->staged || up(c->rtiles, c->rtiles_h.data(), sizeof(RowTile) * c->nrt)) &&
+            (!c->nchunks || up(c->chunks, c->chunks_h.data(), sizeof(RedChunk) * c->nchunks)) &&
             (!c->staged ||
              up(c->cell_tile, cell_tile.data(), sizeof(int32_t) * (size_t)c->ncells)) &&
             hipMemset(c->st, 0, sizeof(DevState)) == hipSuccess &&
@@ -806,31 +852,33 @@ md_status md_get_neighbors(md_ctx c, int32_t rep, int32_t* count, int32_t* ids, 
   HIPCHECK(c, hipMemcpy(cnt.data(), c->ncount + d.off, sizeof(int32_t) * d.n,
                         hipMemcpyDeviceToHost));
   HIPCHECK(c, hipMemcpy(idv.data(), c->id, sizeof(int32_t) * c->ntot, hipMemcpyDeviceToHost));
-  const int32_t rows = std::min(c->cap, cap);
-  std::vector<uint32_t> ell((size_t)std::max(rows, 1) * d.n);
-  if (rows > 0) {
+  // the list slices that hold the replica's particles, one contiguous block
+  const int32_t s0 = (int32_t)(d.off / kSlice), s1 = (int32_t)((d.off + d.n - 1) / kSlice);
+  const size_t lo = (size_t)s0 * kSlice * c->cap, nel = (size_t)(s1 - s0 + 1) * kSlice * c->cap;
+  std::vector<uint32_t> sl(cap > 0 && d.n > 0 ? nel : 1);
+  if (cap > 0 && d.n > 0) {
     const uint32_t* src = c->nbr;
     uint32_t* tmp = nullptr;
     if (c->staged) {
       // staged entries are LDS slots of the home tile: decode to particle indices
-      md_status a_rc = dalloc(c, &tmp, (size_t)rows * c->stride);
+      md_status a_rc = dalloc(c, &tmp, list_elems(c->ntot, c->cap));
       if (a_rc) return a_rc;
-      launch_decode_staged(c->stream, c->nrt, c->rtiles, c->reps, c->cell_start, c->stride, rows,
+      launch_decode_staged(c->stream, c->nrt, c->rtiles, c->reps, c->cell_start, c->cap,
                            c->nbr16, c->ncount, tmp);
       src = tmp;
     }
-    hipError_t e = hipMemcpy2D(ell.data(), sizeof(uint32_t) * d.n, src + d.off,
-                               sizeof(uint32_t) * c->stride, sizeof(uint32_t) * d.n, rows,
-                               hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(sl.data(), src + lo, sizeof(uint32_t) * nel, hipMemcpyDeviceToHost);
     if (tmp) dfree(c, tmp);
-    if (e != hipSuccess) return fail(c, MD_EHIP, "hipMemcpy2D of the neighbour list failed");
+    if (e != hipSuccess) return fail(c, MD_EHIP, "copying the neighbour list failed");
   }
   for (int32_t i = 0; i < d.n; ++i) {
-    const int32_t orig = idv[d.off + i] - d.off;
+    const int32_t g = (int32_t)d.off + i;
+    const int32_t orig = idv[g] - d.off;
     count[orig] = cnt[i];
     const int32_t m = std::min(std::min(cnt[i], c->cap), cap);
+    const size_t b = list_base(g, c->cap) - lo;
     for (int32_t k = 0; k < m; ++k) {
-      const uint32_t e = ell[(size_t)k * d.n + i];
+      const uint32_t e = sl[b + (size_t)k * kSlice];
       ids[(size_t)orig * cap + k] = idv[e & kIdxMask] - d.off;
     }
   }
@@ -926,8 +974,14 @@ md_status md_autotune(md_ctx c, int32_t reps, md_tune* out) {
       d.fb0 = d.tile0 * c->tpp;
       d.fb1 = d.tile1 * c->tpp;
     }
+    plan_chunks(c);
+    if (c->nchunks)
+      HIPCHECK(c, hipMemcpyAsync(c->chunks, c->chunks_h.data(), sizeof(RedChunk) * c->nchunks,
+                                 hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipMemcpyAsync(c->reps, c->reps_h.data(), sizeof(RepDesc) * c->nrep,
                                hipMemcpyHostToDevice, c->stream));
+    // the host vectors are re-planned only here, after the copies finished
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
   }
   drop_graph(c);
   launch_forces0(c);

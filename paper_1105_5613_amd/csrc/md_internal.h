@@ -36,6 +36,19 @@ enum : int32_t {
   kErrType = 8,
 };
 
+// Neighbour lists are stored as sliced ELL: slice s holds particles
+// [256 s, 256 s + 256) and stores its cap rows one after another, row k
+// holding entry k of the slice's 256 particles.  A wave reading entry k of
+// consecutive particles reads contiguous memory, and the whole list of a
+// slice is one contiguous block (a few pages even for very large systems).
+constexpr int32_t kSlice = 256;
+__host__ __device__ inline size_t list_base(int32_t i, int32_t cap) {
+  return (size_t)(i >> 8) * (size_t)cap * kSlice + (size_t)(i & (kSlice - 1));
+}
+inline size_t list_elems(int32_t ntot, int32_t cap) {
+  return (size_t)((ntot + kSlice - 1) / kSlice) * kSlice * (size_t)cap;
+}
+
 struct Tile {          // a run of <= kTile particles of one replica
   int32_t rep;
   int32_t start;
@@ -53,6 +66,7 @@ struct RepDesc {       // per-replica geometry, device resident
   int32_t coff, nc;    // first cell, cells per side
   int32_t tile0, tile1;// tiles [tile0, tile1)
   int32_t fb0, fb1;    // force-kernel partial blocks [fb0, fb1) of this replica
+  int32_t cb0, cb1;    // reduction chunks [cb0, cb1) (two-level reduction only)
   double cside;        // cell side rounded to FP32 (exact in both precisions)
   double cdelta;       // L - nc * cside (periodic-image correction of the mixed form)
 };
@@ -167,13 +181,24 @@ struct ThermoArgs {
   int32_t nlog;
   int32_t pad;
 };
+// First level of the two-level reduction (large replicas): chunk c sums the
+// partial triples [b0, b1) and takes the maximum of the drift tile maxima
+// [t0, t1) into part2[4 c .. 4 c + 3].
+struct RedChunk {
+  int32_t b0, b1, t0, t1;
+};
+constexpr int32_t kRedChunk = 1024;  // partial blocks per chunk
+void launch_reduce_chunks(hipStream_t s, int32_t nchunks, const RedChunk* ch, const double* part,
+                          const double* dmax, int32_t step, double* part2);
 // step = 0: observables of the current state only; step = 1: end of a step
 // part holds one (pe, w, ke) triple per force block; replica r owns blocks
 // [fb0, fb1).  dmax holds the kick/drift tile maxima of |x - x_ref|^2
 // (tiles [tile0, tile1) of replica r), read when step = 1.
+// With part2 != NULL the per-replica pass reads the chunk results
+// part2[4 c + k], c in [cb0, cb1), instead of part and dmax.
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
-                   const double* dmax, int32_t step, ThermoArgs ta, int64_t* kcall, double* lam,
-                   int32_t* rebuild, md_obs* obs, DevState* st);
+                   const double* dmax, const double* part2, int32_t step, ThermoArgs ta,
+                   int64_t* kcall, double* lam, int32_t* rebuild, md_obs* obs, DevState* st);
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* obs,
                         DevState* st);
 void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam);
@@ -201,8 +226,8 @@ void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         int32_t* ncount, DevState* st, const int32_t* cell_tile,
                         const RowTile* rtiles);
 void launch_decode_staged(hipStream_t s, int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
-                          const int32_t* cell_start, int32_t stride, int32_t rows,
-                          const uint16_t* nbr, const int32_t* ncount, uint32_t* out);
+                          const int32_t* cell_start, int32_t cap, const uint16_t* nbr,
+                          const int32_t* ncount, uint32_t* out);
 void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
                          int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
                          const PairTab* tab, const int32_t* cell_start, const double4* pos,

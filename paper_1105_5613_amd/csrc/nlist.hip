@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
   const int32_t ti = (int32_t)p.w;
   const double* thr = &s_thr[ti * 4];
   int32_t cnt = 0;
-  uint32_t* out = nbr + i;
+  uint32_t* out = nbr + list_base(i, cap);
   if (R.nc == 1) {
     // one cell: the minimum image  d - L nearbyint(d / L)
     for (int32_t j = R.off; j < R.off + R.n; ++j) {
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
       double r2 = (ex * ex + ey * ey) + ez * ez;
       if (r2 < thr[(int32_t)q.w]) {
         if (cnt < cap)
-          out[(size_t)cnt * stride] =
+          out[(size_t)cnt * kSlice] =
               (uint32_t)j | image_code(-(int32_t)kx, -(int32_t)ky, -(int32_t)kz);
         ++cnt;
       }
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
               const double ez = (q[u].z + shz) - p.z;
               const double r2 = (ex * ex + ey * ey) + ez * ez;
               if (k + u != i && r2 < thr[(int32_t)q[u].w]) {
-                if (cnt < cap) out[(size_t)cnt * stride] = (uint32_t)(k + u) | code;
+                if (cnt < cap) out[(size_t)cnt * kSlice] = (uint32_t)(k + u) | code;
                 ++cnt;
               }
             }
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
             const double ez = (q.z + shz) - p.z;
             const double r2 = (ex * ex + ey * ey) + ez * ez;
             if (k != i && r2 < thr[(int32_t)q.w]) {
-              if (cnt < cap) out[(size_t)cnt * stride] = (uint32_t)k | code;
+              if (cnt < cap) out[(size_t)cnt * kSlice] = (uint32_t)k | code;
               ++cnt;
             }
           }
@@ -203,7 +203,7 @@ __device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_
       if (k < rows_lds)
         buf[k * gn + hl] = entry;
       else
-        nbr[(size_t)k * stride + ih] = (E)entry;
+        nbr[list_base(ih, cap) + (size_t)k * kSlice] = (E)entry;
     }
     cnt += (int32_t)__popcll(mask);
   }
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
     const int32_t lr = lane / gn, lh = lane - lr * gn;
     if (lr < per)
       for (int32_t kk = lr; kk < rows; kk += per)
-        nbr[(size_t)kk * stride + gbase + lh] = (E)buf[kk * gn + lh];
+        nbr[list_base(gbase + lh, cap) + (size_t)kk * kSlice] = (E)buf[kk * gn + lh];
     // the next group reuses the buffer
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

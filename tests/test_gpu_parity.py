@@ -281,9 +281,51 @@ def test_large_box_sampled(torch_cuda, path):
         e = float(np.max(d / np.maximum(np.linalg.norm(Fo, axis=1), frms)))
         say(f"  precision {precision}: sampled force error {e:.3e}")
         assert e <= (1e-12 if precision == 0 else 1e-5)
+        # totals through the two-level reduction (more than 4,096 partial blocks)
+        ob = sysm.observables()[0]
+        _, pe_i, w_i = oracle.forces_cells(p, x, s["type"], s["L"])
+        tol = 1e-12 if precision == 0 else 1e-6
+        assert ob["pe"] == pytest.approx(float(np.sum(pe_i)), rel=tol)
+        assert ob["virial"] == pytest.approx(float(np.sum(w_i)), rel=tol)
+        m = np.array(initconf.mixture_tables()[3])[s["type"]]
+        ke = 0.5 * float(np.sum(m[:, None] * v.cpu().numpy() ** 2))
+        assert ob["ke"] == pytest.approx(ke, rel=1e-12)
         # the total force vanishes to round-off (full list: both sides of a pair)
         assert np.max(np.abs(F.astype(np.float64).sum(axis=0))) <= \
             (1e-9 if precision == 0 else 1e-2) * np.sum(Fall)
+
+
+def test_67m_mixed_sampled(torch_cuda):
+    """One GPU's large share: 67,108,864 particles, mixed precision, after 10
+    steps.  Cell arrays bit-exact over the whole box; forces of 4,096 sampled
+    particles against the oracle's cell-list forces (the full neighbour list,
+    about 50 GB on the host, is checked through those forces)."""
+    say("case 67M mixed")
+    from paper_1105_5613_amd import System
+    n = 67108864
+    s = initconf.fcc_system(n, seed=3, temperature=2.0)
+    sysm = System(lib_params(precision=1), [n], [s["L"]])
+    sysm.set_state(s["x"], s["v"], s["type"])
+    sysm.step(10)
+    x = sysm.get_state()[0].cpu().numpy()
+    sysm.build_cells()
+    p = oracle_params()
+    _, _, _, cs, order, nc = oracle.build_cells(p, x, s["L"])
+    gcs, gorder = sysm.get_cells(0)
+    assert sysm.replica_info(0)["nc"] == nc == 136
+    assert np.array_equal(gcs, cs) and np.array_equal(gorder, order)
+    del gcs, gorder, cs, order
+    sysm.forces()
+    F = sysm.get_forces().cpu().numpy()
+    sel = np.random.default_rng(5).choice(n, 4096, replace=False)
+    Fo, _, _ = oracle.forces_cells(p, x, s["type"], s["L"], sel=sel)
+    frms = float(np.sqrt(np.mean(np.sum(F.astype(np.float64) ** 2, axis=1))))
+    d = np.linalg.norm(F[sel].astype(np.float64) - Fo, axis=1)
+    e = float(np.max(d / np.maximum(np.linalg.norm(Fo, axis=1), frms)))
+    say(f"  sampled force error {e:.3e}")
+    assert e <= 1e-5
+    ob = sysm.observables()[0]
+    assert np.isfinite(ob["E"]) and ob["n_rebuild"] >= 2
 
 
 @pytest.mark.parametrize("path", ["gather", "staged"])
