@@ -67,8 +67,12 @@ enum { MD_FP64 = 0, MD_MIXED = 1 };
  * of cells (about 128 home particles) copies the tile's 27-piece
  * neighbourhood, with periodic shifts applied, into LDS once per force
  * launch, and list entries are 16-bit LDS slots; needs >= 3 cells per box
- * side.  AUTO is GATHER. */
-enum { MD_PATH_AUTO = 0, MD_PATH_GATHER = 1, MD_PATH_STAGED = 2 };
+ * side.  CELLS: the paper's list-free linked-cell evaluation ("Grid-search
+ * method", Fig. 1): no neighbour list at all, every force launch searches
+ * the 27-cell stencil of each particle (cells rebuilt by the skin rule);
+ * needs >= 3 cells per box side; md_get_neighbors and md_list_stats return
+ * MD_ESTATE.  AUTO is GATHER. */
+enum { MD_PATH_AUTO = 0, MD_PATH_GATHER = 1, MD_PATH_STAGED = 2, MD_PATH_CELLS = 3 };
 #define MD_MAXT 4
 
 /* Physical and numerical parameters, shared by all replicas of a context. */
@@ -91,7 +95,7 @@ typedef struct {
                             path 1,2,4); 0 = auto */
   int32_t unroll;        /* list slots gathered per pipelined chunk in the force
                             kernel (1,2,4,8); 0 = auto */
-  int32_t path;          /* MD_PATH_AUTO, MD_PATH_GATHER or MD_PATH_STAGED */
+  int32_t path;          /* MD_PATH_AUTO, MD_PATH_GATHER, MD_PATH_STAGED or MD_PATH_CELLS */
   int32_t tile_cells;    /* staged path: cells per row tile (1..64); 0 = auto */
   int32_t stage_slots;   /* staged path: LDS slots per tile (>= 64); slots beyond are
                             read from global memory; 0 = auto */

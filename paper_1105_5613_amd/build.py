@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-x", "hip",
           "-I", os.path.join(HERE, "..", "include")]
 PER_FILE = {"nlist.hip": ["-ffp-contract=off"],
             "analysis.hip": ["-ffp-contract=off"]}
-SOURCES = ["cells.hip", "nlist.hip", "force.hip", "force_staged.hip",
+SOURCES = ["cells.hip", "nlist.hip", "force.hip", "force_staged.hip", "force_cells.hip",
            "integrate.hip", "analysis.hip", "md_api.cpp"]
 
 

@@ -20,6 +20,7 @@ struct md_ctx_s {
   int32_t mixed = 0;
   // staged path (row tiles with LDS-staged neighbourhoods)
   int32_t staged = 0, nrt = 0, lcap_f = 0;
+  int32_t cells = 0;  // list-free cell path (row tiles, no neighbour list)
   int32_t any_single = 0, any_multi = 0;  // replicas with one cell / with >= 3 per side
   std::vector<RowTile> rtiles_h;
   RowTile* rtiles = nullptr;
@@ -162,7 +163,7 @@ md_status validate(const md_params* p, std::string* why) {
   if (p->graph_steps < 0) return *why = "graph_steps must be >= 0", MD_EINVAL;
   if (p->unroll != 0 && p->unroll != 1 && p->unroll != 2 && p->unroll != 4 && p->unroll != 8)
     return *why = "unroll must be 0, 1, 2, 4 or 8", MD_EINVAL;
-  if (p->path < MD_PATH_AUTO || p->path > MD_PATH_STAGED) return *why = "unknown path", MD_EINVAL;
+  if (p->path < MD_PATH_AUTO || p->path > MD_PATH_CELLS) return *why = "unknown path", MD_EINVAL;
   if (p->tile_cells < 0 || p->tile_cells > kMaxRowCells)
     return *why = "tile_cells must be 0..64", MD_EINVAL;
   if (p->stage_slots != 0 && p->stage_slots < 64) return *why = "stage_slots must be 0 or >= 64", MD_EINVAL;
@@ -195,7 +196,10 @@ void run_chain(md_ctx c, hipStream_t s) {
                  c->tmp_src);
   launch_cell_gather(s, c->ncells, c->cell_rep, c->rebuild, c->cell_start, c->tmp_src, c->stride,
                      c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp);
-  if (c->staged)
+  if (c->cells)
+    launch_commit_order(s, c->ntiles, c->tiles, c->rebuild, c->stride, c->pos_tmp, c->vel_tmp,
+                        c->id_tmp, c->pos, c->vel, c->id, c->xref);
+  else if (c->staged)
     launch_nlist_tiles(s, c->ncells, c->cell_rep, c->reps, c->rebuild, c->tab, c->cell_start,
                        c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
                        c->xref, c->nbr16, c->ncount, c->st, c->cell_tile, c->rtiles);
@@ -207,7 +211,10 @@ void run_chain(md_ctx c, hipStream_t s) {
 }
 
 void launch_forces(md_ctx c, int32_t mode, hipStream_t s) {
-  if (c->staged)
+  if (c->cells)
+    launch_force_cells(s, c->mixed, mode, c->nrt, c->rtiles, c->reps, c->tab, c->cell_start,
+                       c->pos, c->vel, c->frc, c->stride, c->p.dt, c->part, c->st);
+  else if (c->staged)
     launch_force_staged(s, c->mixed, mode, c->tpp, c->unroll, c->nrt, c->rtiles, c->reps,
                         c->tab, c->cell_start, c->pos, c->vel, c->frc, c->nbr16, c->ncount,
                         c->stride, c->cap, c->lcap_f, c->p.dt, c->part, c->st);
@@ -454,12 +461,13 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     if (d.nc == 1) c->any_single = 1;
     else c->any_multi = 1;
   }
-  if (p->path == MD_PATH_STAGED && !all3) {
+  if ((p->path == MD_PATH_STAGED || p->path == MD_PATH_CELLS) && !all3) {
     delete c;
-    return fail(nullptr, MD_EINVAL, "the staged path needs >= 3 cells per box side");
+    return fail(nullptr, MD_EINVAL, "the staged and cell paths need >= 3 cells per box side");
   }
   c->staged = p->path == MD_PATH_STAGED;
-  if (c->mixed && !c->staged)
+  c->cells = p->path == MD_PATH_CELLS;
+  if (c->mixed && !c->staged && !c->cells)
     for (const RepDesc& d : c->reps_h)
       if (d.nc > 1023) {
         delete c;
@@ -476,14 +484,15 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     (void)hipGetLastError();
     lds_max = std::min(lds_max, 65536);  // stay within the default per-block limit
   }
-  if (c->staged) {
-    if (c->tpp == 8) {
+  if (c->staged || c->cells) {
+    if (c->staged && c->tpp == 8) {
       delete c;
       return fail(nullptr, MD_EINVAL, "the staged path takes tpp 1, 2 or 4");
     }
-    // row tiles of about kStageHomes home particles; LDS holds the tile's
-    // 9 x (nx + 2) cells with 30 % headroom (denser tiles spill to global)
-    const int32_t homes = staged_homes_per_group();
+    // row tiles of about 128 home particles; on the staged path LDS holds the
+    // tile's 9 x (nx + 2) cells with 30 % headroom (denser tiles spill to
+    // global memory)
+    const int32_t homes = c->cells ? cells_homes_per_block() : staged_homes_per_group();
     double need = 0.0;
     for (int r = 0; r < nrep; ++r) {
       RepDesc& d = c->reps_h[r];
@@ -597,11 +606,13 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     ALLOC(f, 3 * S);
     c->frc = f;
   }
-  if (c->mixed && !c->staged) ALLOC(c->pos16, S);
+  if (c->mixed && !c->staged && !c->cells) ALLOC(c->pos16, S);
   ALLOC(c->id, N);
   ALLOC(c->id_tmp, N);
   ALLOC(c->img, 3 * N);
-  if (c->staged) {
+  if (c->cells) {
+    ALLOC(c->rtiles, (size_t)c->nrt);
+  } else if (c->staged) {
     ALLOC(c->nbr16, list_elems(c->ntot, c->cap));
     ALLOC(c->cell_tile, (size_t)c->ncells);
     ALLOC(c->rtiles, (size_t)c->nrt);
@@ -641,7 +652,8 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
             up(c->tab, &tab, sizeof(PairTab)) &&
             up(c->cell_rep, cell_rep.data(), sizeof(int32_t) * c->ncells) &&
             up(c->lam, ones.data(), sizeof(double) * nrep) &&
-            (!c->staged || up(c->rtiles, c->rtiles_h.data(), sizeof(RowTile) * c->nrt)) &&
+            (!(c->staged || c->cells) ||
+             up(c->rtiles, c->rtiles_h.data(), sizeof(RowTile) * c->nrt)) &&
             (!c->nchunks || up(c->chunks, c->chunks_h.data(), sizeof(RedChunk) * c->nchunks)) &&
             (!c->staged ||
              up(c->cell_tile, cell_tile.data(), sizeof(int32_t) * (size_t)c->ncells)) &&
@@ -842,6 +854,7 @@ md_status md_get_cells(md_ctx c, int32_t rep, int32_t* cell_start, int32_t* orde
 
 md_status md_get_neighbors(md_ctx c, int32_t rep, int32_t* count, int32_t* ids, int32_t cap) {
   if (!c) return MD_EINVAL;
+  if (c->cells) return fail(c, MD_ESTATE, "the cell path keeps no neighbour list");
   if (rep < 0 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
   if (!c->built) return fail(c, MD_ESTATE, "list not built");
   if (!count || (cap > 0 && !ids) || cap < 0) return fail(c, MD_EINVAL, "bad output buffers");
@@ -931,7 +944,9 @@ md_status md_autotune(md_ctx c, int32_t reps, md_tune* out) {
     if (rc) return rc;
   }
   std::vector<std::pair<int32_t, int32_t>> cand;
-  if (c->staged)
+  if (c->cells)
+    cand = {{1, 1}};  // one kernel variant: nothing to choose
+  else if (c->staged)
     cand = {{1, 4}, {1, 8}, {2, 2}, {2, 4}, {2, 8}, {4, 2}};
   else
     cand = {{1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 1}, {4, 2}, {8, 1}};
@@ -968,7 +983,7 @@ md_status md_autotune(md_ctx c, int32_t reps, md_tune* out) {
   (void)hipEventDestroy(e1);
   c->tpp = btpp;
   c->unroll = bun;
-  if (!c->staged) {
+  if (!c->staged && !c->cells) {
     // partial-sum blocks per replica follow the lanes per particle
     for (RepDesc& d : c->reps_h) {
       d.fb0 = d.tile0 * c->tpp;
@@ -1049,6 +1064,7 @@ md_status md_rdf(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g) {
 
 md_status md_list_stats(md_ctx c, int32_t rep, double* mean, int32_t* max) {
   if (!c) return MD_EINVAL;
+  if (c->cells) return fail(c, MD_ESTATE, "the cell path keeps no neighbour list");
   if (rep < -1 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
   if (!c->built) return fail(c, MD_ESTATE, "list not built");
   md_status rc = sync_and_check(c);

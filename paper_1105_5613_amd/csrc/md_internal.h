@@ -228,6 +228,16 @@ void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
 void launch_decode_staged(hipStream_t s, int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
                           const int32_t* cell_start, int32_t cap, const uint16_t* nbr,
                           const int32_t* ncount, uint32_t* out);
+// list-free cell path (force_cells.hip)
+int32_t cells_homes_per_block();
+void launch_force_cells(hipStream_t s, int32_t mixed, int32_t mode, int32_t nrt,
+                        const RowTile* rtiles, const RepDesc* reps, const PairTab* tab,
+                        const int32_t* cell_start, const double4* pos, double* vel, void* frc,
+                        int32_t stride, double dt, double* part, DevState* st);
+void launch_commit_order(hipStream_t s, int32_t ntiles, const Tile* tiles,
+                         const int32_t* rebuild, int32_t stride, const double4* pos_tmp,
+                         const double* vel_tmp, const int32_t* id_tmp, double4* pos,
+                         double* vel, int32_t* id, double* xref);
 void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
                          int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
                          const PairTab* tab, const int32_t* cell_start, const double4* pos,

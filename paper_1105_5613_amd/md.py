@@ -21,7 +21,7 @@ MD_OK, MD_EINVAL, MD_ENOMEM, MD_EBOX, MD_EOVERFLOW, MD_ENONFINITE, MD_EHIP, MD_E
 MD_FP64, MD_MIXED = 0, 1
 MD_POT_LJ, MD_POT_SOFT = 0, 1
 MD_TRUNC_SHIFTED_FORCE, MD_TRUNC_SHIFT = 0, 1
-MD_PATH_AUTO, MD_PATH_GATHER, MD_PATH_STAGED = 0, 1, 2
+MD_PATH_AUTO, MD_PATH_GATHER, MD_PATH_STAGED, MD_PATH_CELLS = 0, 1, 2, 3
 
 EXPORTS = ["md_init", "md_destroy", "md_last_error", "md_set_state", "md_get_state",
            "md_build_cells", "md_forces", "md_get_forces", "md_step", "md_observables",
