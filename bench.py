@@ -77,24 +77,27 @@ def mixture():
     return initconf.mixture_tables()
 
 
-def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int):
+def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int,
+               path: int = 1, potential: int = 0, global_rc=None, dt: float = 0.005, T0=None):
     from paper_1105_5613_amd import System, make_params
-    eps, sig, rc, mass = mixture()
-    p = make_params(eps, sig, rc, mass, skin=0.3, dt=0.005, precision=precision)
+    import initconf
+    eps, sig, rc, mass = initconf.mixture_tables(global_rc=global_rc)
+    p = make_params(eps, sig, rc, mass, skin=0.3, dt=dt, precision=precision, path=path,
+                    potential=potential)
     n = inputs["n"]
     sysm = System(p, [n], [inputs["L"]])
     sysm.set_state(inputs["x"], inputs["v"], inputs["type"])
-    sysm.step(warmup)
+    sysm.step(warmup, T0=T0)
     tuned = sysm.autotune(reps=3)
     sysm.profile(prof_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sysm.step(steps)
+    sysm.step(steps, T0=T0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = sysm.profile_read()
     sysm.profile(0)
-    nbar, nmax = sysm.list_stats()
+    nbar, nmax = (0.0, 0) if path == 3 else sysm.list_stats()
     obs = sysm.observables()[0]
     sysm.close()
     return {"wall_s": wall, "rate": n * steps / wall, "ms_per_step": 1e3 * wall / steps,
@@ -233,7 +236,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--forms", default="fp64,mixed,large,batched")
+    ap.add_argument("--forms", default="fp64,mixed,large,batched,cells,soft")
     ap.add_argument("--profile-every", type=int, default=4,
                     help="bracket the force launch of every k-th timed step with hipEvents")
     ap.add_argument("--cpu-steps", type=int, default=40)
@@ -317,6 +320,31 @@ def main():
             "force_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
             "mean_list_length": round(rl["nbar"], 3), "rebuilds": rl["rebuilds"],
             "tuned": rl["tuned"]}
+    if "cells" in forms:
+        log(f"timing the list-free cell path (FP64): {args.steps} steps")
+        rcell = run_single(torch, 0, inputs, args.steps, args.warmup, args.profile_every, path=3)
+        log(f"  cell path: {rcell['rate']:.4e} particle-steps/s, {rcell['ms_per_step']:.4f} ms/step, "
+            f"force {rcell['force_ms_avg']:.4f} ms")
+        forms_out["cells_fp64"] = {
+            "workload": f"lj{n} as the headline, list-free cell path (no neighbour list; the "
+                        "27-cell stencil searched in every force launch)",
+            "value": round(rcell["rate"], 1), "ms_per_step": round(rcell["ms_per_step"], 5),
+            "force_ms_avg": round(rcell["force_ms_avg"], 5), "rebuilds": rcell["rebuilds"]}
+        if "fp64" in res:
+            forms_out["cells_fp64"]["rate_vs_list_fp64"] = round(rcell["rate"] / res["fp64"]["rate"], 4)
+    if "soft" in forms:
+        log(f"timing the soft-sphere workload: {args.steps} steps")
+        soft_in = initconf.fcc_system(n, seed=6, temperature=0.5)
+        rs = run_single(torch, 0, soft_in, args.steps, args.warmup, args.profile_every,
+                        potential=1, global_rc=1.2, dt=0.001, T0=0.5)
+        del soft_in
+        log(f"  soft sphere: {rs['rate']:.4e} particle-steps/s, {rs['ms_per_step']:.4f} ms/step")
+        forms_out["soft_fp64"] = {
+            "workload": f"soft{n}: binary soft-sphere mixture Eq. (2), rho 1.2, canonical T=0.5 "
+                        "(velocity rescale), rc=1.2 for every pair, dt 0.001, skin 0.3, FP64",
+            "value": round(rs["rate"], 1), "ms_per_step": round(rs["ms_per_step"], 5),
+            "force_ms_avg": round(rs["force_ms_avg"], 5),
+            "mean_list_length": round(rs["nbar"], 3), "rebuilds": rs["rebuilds"]}
     if "batched" in forms:
         log(f"timing batched replicas: {args.replicas} boxes, {args.batched_steps} steps")
         systems, temps = replica_inputs(args.replicas)

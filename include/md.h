@@ -227,9 +227,11 @@ md_status md_msd(md_ctx ctx, double* out);
 
 /* Radial distribution function of replica rep (glass section):
  * g[b] = 2V/N^2 * (number of pairs i < j with b dr <= r_ij < (b+1) dr) / shell
- * volume of bin b, dr = rmax / nbins, minimum image, exact FP64 distances
- * over all pairs.  rmax <= L/2, nbins <= 8192, replica size <= 262144.
- * g HOST [nbins].  Synchronises. */
+ * volume of bin b, dr = rmax / nbins, minimum image, exact FP64 distances.
+ * With rmax <= cell side - skin (and >= 3 cells per side) the pairs come
+ * from the cell grid (any replica size; builds the cells first if needed);
+ * otherwise all pairs are visited and the replica may hold at most 262144
+ * particles.  rmax <= L/2, nbins <= 8192.  g HOST [nbins].  Synchronises. */
 md_status md_rdf(md_ctx ctx, int32_t rep, double rmax, int32_t nbins, double* g);
 
 /* Neighbour-list statistics of replica rep (rep = -1: all replicas) at the

@@ -360,17 +360,27 @@ int mdref_rdf(int64_t n, double L, const double* x, double rmax,
   double dr = rmax / nbins;
   long double* h = (long double*)calloc((size_t)nbins, sizeof(long double));
   if (!h) return -3;
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t j = i + 1; j < n; ++j) {
-      double d[3];
-      for (int q = 0; q < 3; ++q) d[q] = min_image(x[3 * i + q] - x[3 * j + q], L);
-      double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      if (r < rmax) {
-        int32_t b = (int32_t)(r / dr);
-        if (b >= nbins) b = nbins - 1;
-        h[b] += 1.0L;
+  /* pair counts per bin: integers, so splitting the rows over threads and
+     adding the per-thread counts gives exactly the serial histogram */
+#pragma omp parallel
+  {
+    int64_t* hl = (int64_t*)calloc((size_t)nbins, sizeof(int64_t));
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = i + 1; j < n; ++j) {
+        double d[3];
+        for (int q = 0; q < 3; ++q) d[q] = min_image(x[3 * i + q] - x[3 * j + q], L);
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (r < rmax) {
+          int32_t b = (int32_t)(r / dr);
+          if (b >= nbins) b = nbins - 1;
+          if (hl) hl[b] += 1;
+        }
       }
-    }
+#pragma omp critical
+    for (int32_t b = 0; b < nbins; ++b) h[b] += (long double)(hl ? hl[b] : 0);
+    free(hl);
+  }
   double V = L * L * L;
   const double pi = 3.14159265358979323846;
   for (int32_t b = 0; b < nbins; ++b) {

@@ -125,7 +125,90 @@ __global__ __launch_bounds__(kRdfTile) void k_rdf(const double4* __restrict__ po
     if (s_h[b]) atomicAdd(&hist[b], (unsigned long long)s_h[b]);
 }
 
+// Pair-distance histogram over the cells of replica [c0, c0 + nc^3): one
+// wave per home cell; the lanes take packed candidates of the 27 neighbour
+// cells (distinct for nc >= 3), the wave walks the home particles, and each
+// unordered pair is counted once (sorted partner index above the home's).
+// Distances use the same minimum-image arithmetic as k_rdf; every pair
+// closer than the cell side minus the skin is in the stencil while the
+// skin rule holds.
+__global__ __launch_bounds__(256) void k_rdf_cells(int32_t c0, int32_t nc,
+                                                   const int32_t* __restrict__ cell_start,
+                                                   const double4* __restrict__ pos, double L,
+                                                   double rmax, double dr, int32_t nbins,
+                                                   unsigned long long* __restrict__ hist) {
+  extern __shared__ unsigned int s_h[];
+  __shared__ int32_t s_pre[4][28], s_k0[4][27];
+  for (int b = threadIdx.x; b < nbins; b += 256) s_h[b] = 0u;
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t lc = (int32_t)blockIdx.x * 4 + w;
+  if (lc < nc * nc * nc) {
+    const int32_t qx = lc % nc, qy = (lc / nc) % nc, qz = lc / (nc * nc);
+    const int32_t h0 = cell_start[c0 + lc], nh = cell_start[c0 + lc + 1] - h0;
+    if (lane < 27) {
+      const int32_t nx = (qx + lane % 3 - 1 + nc) % nc, ny = (qy + (lane / 3) % 3 - 1 + nc) % nc,
+                    nz = (qz + lane / 9 - 1 + nc) % nc;
+      const int32_t cn = c0 + (nz * nc + ny) * nc + nx;
+      s_k0[w][lane] = cell_start[cn];
+      s_pre[w][lane] = cell_start[cn + 1] - cell_start[cn];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      int32_t acc = 0;
+      for (int p = 0; p < 27; ++p) {
+        const int32_t len = s_pre[w][p];
+        s_pre[w][p] = acc;
+        acc += len;
+      }
+      s_pre[w][27] = acc;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int32_t ncand = s_pre[w][27];
+    for (int32_t base = 0; base < ncand; base += 64) {
+      const int32_t v = base + lane;
+      const bool valid = v < ncand;
+      int p = 0;
+#pragma unroll
+      for (int step = 16; step >= 1; step >>= 1)
+        if (p + step <= 26 && s_pre[w][p + step] <= v) p += step;
+      const int32_t k = valid ? s_k0[w][p] + (v - s_pre[w][p]) : h0;
+      const double4 q = pos[k];
+      for (int32_t h = 0; h < nh; ++h) {
+        const int32_t i = __builtin_amdgcn_readfirstlane(h0 + h);
+        const double4 pa = pos[i];
+        if (valid && k > i) {
+          double dx = pa.x - q.x, dy = pa.y - q.y, dz = pa.z - q.z;
+          const double kx = rint(dx / L), ky = rint(dy / L), kz = rint(dz / L);
+          const double tx = L * kx, ty = L * ky, tz = L * kz;
+          dx = dx - tx;
+          dy = dy - ty;
+          dz = dz - tz;
+          const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+          if (r < rmax) {
+            int32_t b = (int32_t)(r / dr);
+            b = b >= nbins ? nbins - 1 : b;
+            atomicAdd(&s_h[b], 1u);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += 256)
+    if (s_h[b]) atomicAdd(&hist[b], (unsigned long long)s_h[b]);
+}
+
 }  // namespace
+
+void launch_rdf_cells(hipStream_t s, int32_t c0, int32_t nc, const int32_t* cell_start,
+                      const double4* pos, double L, double rmax, int32_t nbins,
+                      unsigned long long* hist) {
+  const double dr = rmax / nbins;
+  const int32_t ncell = nc * nc * nc;
+  k_rdf_cells<<<(ncell + 3) / 4, 256, sizeof(unsigned int) * nbins, s>>>(
+      c0, nc, cell_start, pos, L, rmax, dr, nbins, hist);
+}
 
 void launch_msd_ref(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                     const double4* pos, const int32_t* id, const int32_t* img, double* u0) {

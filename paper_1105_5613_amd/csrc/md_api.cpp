@@ -1039,12 +1039,27 @@ md_status md_rdf(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g) {
   const RepDesc& d = c->reps_h[rep];
   if (!g || nbins < 1 || nbins > 8192 || !(rmax > 0.0) || rmax > 0.5 * d.L)
     return fail(c, MD_EINVAL, "need g, 1 <= nbins <= 8192 and 0 < rmax <= L/2");
-  if (d.n > 262144) return fail(c, MD_EINVAL, "md_rdf supports replicas of up to 262144 particles");
+  // the cell sweep covers every pair closer than the cell side minus the
+  // skin while the skin rule holds; otherwise all pairs are visited
+  const bool by_cells = d.nc >= 3 && rmax <= d.L / d.nc - c->p.skin;
+  if (!by_cells && d.n > 262144)
+    return fail(c, MD_EINVAL,
+                "md_rdf: rmax above the cell side minus the skin needs a replica of at most "
+                "262144 particles");
+  if (by_cells && !c->built) {
+    md_status b = build_all(c);
+    if (b) return b;
+  }
   unsigned long long* hist = nullptr;
   md_status rc = dalloc(c, &hist, (size_t)nbins);
   if (rc) return rc;
   hipError_t e = hipMemsetAsync(hist, 0, sizeof(unsigned long long) * nbins, c->stream);
-  if (e == hipSuccess) launch_rdf(c->stream, c->pos, d.off, d.n, d.L, rmax, nbins, hist);
+  if (e == hipSuccess) {
+    if (by_cells)
+      launch_rdf_cells(c->stream, d.coff, d.nc, c->cell_start, c->pos, d.L, rmax, nbins, hist);
+    else
+      launch_rdf(c->stream, c->pos, d.off, d.n, d.L, rmax, nbins, hist);
+  }
   std::vector<unsigned long long> h(nbins);
   rc = sync_and_check(c);
   if (!rc && e == hipSuccess)

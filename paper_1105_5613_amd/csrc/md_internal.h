@@ -213,6 +213,9 @@ void launch_msd(hipStream_t s, int32_t ntiles, int32_t nrep, const Tile* tiles,
                 const double* u0, double* part, double* out);
 void launch_rdf(hipStream_t s, const double4* pos, int32_t off, int32_t n, double L, double rmax,
                 int32_t nbins, unsigned long long* hist);
+void launch_rdf_cells(hipStream_t s, int32_t c0, int32_t nc, const int32_t* cell_start,
+                      const double4* pos, double L, double rmax, int32_t nbins,
+                      unsigned long long* hist);
 
 // staged path (stage.h, nlist.hip tile mode, force_staged.hip)
 struct RowTile;

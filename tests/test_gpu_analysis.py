@@ -44,6 +44,26 @@ def test_rdf_matches_oracle(torch_cuda, n, seed, nbins):
     np.testing.assert_allclose(g, go, rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("n,seed,rmax,steps", [(32000, 24, 2.5, 0), (20000, 25, 2.45, 30)])
+def test_rdf_cells_matches_oracle(torch_cuda, n, seed, rmax, steps):
+    """rmax below the cell side minus the skin: pairs from the cell grid,
+    also on a stepped state between list builds; counts bit-exact."""
+    from paper_1105_5613_amd import System
+    say(f"case rdf by cells n={n}")
+    s = initconf.fcc_system(n, seed=seed, jitter=0.2)
+    sysm = System(lib_params(), [n], [s["L"]])
+    sysm.set_state(s["x"], s["v"], s["type"])
+    if steps:
+        sysm.step(steps)
+    info = sysm.replica_info(0)
+    assert rmax <= s["L"] / info["nc"] - 0.3
+    x = sysm.get_state()[0].cpu().numpy()
+    g = sysm.rdf(0, rmax, 250)
+    go = oracle.rdf(x, s["L"], rmax, 250)
+    assert np.array_equal(_counts(g, n, s["L"], rmax, 250), _counts(go, n, s["L"], rmax, 250))
+    np.testing.assert_allclose(g, go, rtol=1e-13, atol=0)
+
+
 def test_rdf_batched_replica(torch_cuda):
     from paper_1105_5613_amd import System
     say("case rdf batched")
@@ -53,10 +73,10 @@ def test_rdf_batched_replica(torch_cuda):
     sysm = System(lib_params(), n, L)
     sysm.set_state(x, v, ty)
     for r, sy in enumerate(systems):
-        rmax = 0.45 * sy["L"]
-        g = sysm.rdf(r, rmax, 200)
-        go = oracle.rdf(sy["x"], sy["L"], rmax, 200)
-        np.testing.assert_allclose(g, go, rtol=1e-13, atol=0)
+        for rmax in (0.45 * sy["L"], 2.0):  # all pairs, then the cell sweep
+            g = sysm.rdf(r, rmax, 200)
+            go = oracle.rdf(sy["x"], sy["L"], rmax, 200)
+            np.testing.assert_allclose(g, go, rtol=1e-13, atol=0)
 
 
 def test_rdf_rejects_bad_arguments(torch_cuda):
