@@ -50,7 +50,8 @@ def test_rdf_cells_matches_oracle(torch_cuda, n, seed, rmax, steps):
     also on a stepped state between list builds; counts bit-exact."""
     from paper_1105_5613_amd import System
     say(f"case rdf by cells n={n}")
-    s = initconf.fcc_system(n, seed=seed, jitter=0.2)
+    # a jittered lattice for a static state; a liquid reached by stepping otherwise
+    s = initconf.fcc_system(n, seed=seed, jitter=0.05 if steps else 0.2)
     sysm = System(lib_params(), [n], [s["L"]])
     sysm.set_state(s["x"], s["v"], s["type"])
     if steps:
