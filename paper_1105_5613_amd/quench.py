@@ -4,7 +4,7 @@ linearly to a low one with the isokinetic velocity rescale, logging per
 replica the potential energy per particle, the temperature and the
 mean-squared displacement from the start of the quench (unwrapped
 positions).  The caloric curve U(T) of the log gives the glass-transition
-estimate as the temperature where its slope changes (two-line fit).
+estimate as the temperature where its slope stops rising (caloric_slope).
 
     python -m paper_1105_5613_amd.quench --replicas 64 --n 131072 \\
         --equil 10000 --quench 100000 --log-every 1000 --out quench.json
@@ -21,27 +21,28 @@ import numpy as np
 from . import md
 
 
-def caloric_break(T, U):
-    """Glass-transition estimate from a caloric curve: the breakpoint of the
-    continuous two-segment linear least-squares fit of U(T) (the temperature
-    where the slope changes), searched on a fine grid of candidate
-    breakpoints between the second and the second-to-last temperature.
-    Returns (T_break, slope_low, slope_high)."""
+def caloric_slope(T, U, window: int = 9):
+    """Apparent heat capacity of a cooling curve and its glass-transition
+    estimate.  The slope dU/dT is taken from least-squares lines over sliding
+    windows of `window` consecutive temperatures; on cooling it rises while
+    the liquid stays in equilibrium and falls once the structure freezes, so
+    the temperature of the largest slope marks the change of slope.
+    Returns (T_centres, slopes, T_at_max_slope, max_slope, slope_coldest)."""
     T = np.asarray(T, dtype=np.float64)
     U = np.asarray(U, dtype=np.float64)
+    if len(T) < window + 2 or window < 3:
+        raise ValueError("caloric_slope needs window >= 3 and more than window + 1 points")
     o = np.argsort(T)
     T, U = T[o], U[o]
-    best = (np.inf, None)
-    if len(T) < 5:
-        raise ValueError("caloric_break needs at least 5 points")
-    for tb in np.linspace(T[1], T[-2], 512):
-        # U = a + b (T - tb) for T < tb, a + c (T - tb) for T >= tb
-        A = np.stack([np.ones_like(T), np.minimum(T - tb, 0.0), np.maximum(T - tb, 0.0)], 1)
-        coef, *_ = np.linalg.lstsq(A, U, rcond=None)
-        r = float(np.sum((A @ coef - U) ** 2))
-        if r < best[0]:
-            best = (r, (float(tb), float(coef[1]), float(coef[2])))
-    return best[1]
+    tc, sl = [], []
+    for k in range(len(T) - window + 1):
+        t, u = T[k:k + window], U[k:k + window]
+        b = np.polyfit(t, u, 1)[0]
+        tc.append(float(t.mean()))
+        sl.append(float(b))
+    tc, sl = np.array(tc), np.array(sl)
+    m = int(np.argmax(sl))
+    return tc, sl, float(tc[m]), float(sl[m]), float(sl[0])
 
 
 def run_quench(nrep: int, n: int, *, seed: int = 5, precision: int = md.MD_MIXED,
@@ -146,9 +147,9 @@ def main(argv=None):
                      quench=a.quench, log_every=a.log_every, nve=a.nve,
                      progress=lambda m: print(m, file=sys.stderr, flush=True))
     pe = np.mean(np.asarray(res["pe_per_particle"]), axis=1)
-    if len(pe) >= 5:
-        tb, lo, hi = caloric_break(res["T_target"], pe)
-        res["caloric_break"] = {"T": tb, "slope_low_T": lo, "slope_high_T": hi}
+    if len(pe) >= 11:
+        _, _, tg, smax, scold = caloric_slope(res["T_target"], pe)
+        res["caloric_slope"] = {"T_max_slope": tg, "max_slope": smax, "slope_coldest": scold}
     if a.one_at_a_time_steps > 0:
         r1 = one_at_a_time_rate(a.replicas, a.n, seed=a.seed, steps=a.one_at_a_time_steps)
         res["one_at_a_time_fp64_rate"] = r1
@@ -158,7 +159,7 @@ def main(argv=None):
         with open(a.out, "w") as f:
             f.write(txt)
     keys = ("replicas", "n", "precision", "quench", "rate", "quench_wall_s",
-            "one_at_a_time_fp64_rate", "speedup_vs_one_at_a_time_fp64", "caloric_break")
+            "one_at_a_time_fp64_rate", "speedup_vs_one_at_a_time_fp64", "caloric_slope")
     print(json.dumps({k: res[k] for k in keys if k in res}), flush=True)
 
 

@@ -1,27 +1,30 @@
-"""Host logic of the quench driver: the caloric-curve breakpoint fit."""
+"""Host logic of the quench driver: the caloric-curve slope estimator."""
+from math import erf
+
 import numpy as np
 import pytest
 
-from paper_1105_5613_amd.quench import caloric_break
+from paper_1105_5613_amd.quench import caloric_slope
 
 
-def test_break_of_exact_two_line_curve():
-    T = np.linspace(0.3, 2.0, 35)
-    U = np.where(T < 0.62, -7.0 + 1.5 * (T - 0.62), -7.0 + 3.2 * (T - 0.62))
-    tb, lo, hi = caloric_break(T, U)
-    assert tb == pytest.approx(0.62, abs=0.004)
-    assert lo == pytest.approx(1.5, rel=1e-2) and hi == pytest.approx(3.2, rel=1e-2)
+def test_slope_of_a_line_is_constant():
+    T = np.linspace(0.3, 2.0, 40)
+    tc, sl, _, smax, scold = caloric_slope(T, 3.0 + 1.5 * T, window=7)
+    assert np.allclose(sl, 1.5) and smax == pytest.approx(1.5) and scold == pytest.approx(1.5)
+    assert len(tc) == len(T) - 6 and np.all(np.diff(tc) > 0)
 
 
-def test_break_with_noise_and_unsorted_input():
-    rng = np.random.default_rng(3)
-    T = rng.permutation(np.linspace(0.3, 2.0, 60))
-    U = np.where(T < 1.1, 2.0 * (T - 1.1), 4.0 * (T - 1.1)) + rng.normal(0, 0.002, T.size)
-    tb, lo, hi = caloric_break(T, U)
-    assert abs(tb - 1.1) < 0.03
-    assert lo < hi
+def test_peak_of_the_slope_is_found_from_unsorted_samples():
+    # U = T + integral of exp(-(t - 0.6)^2 / w): dU/dT = 1 + exp(-(T - 0.6)^2 / w), peak at 0.6
+    w = 0.02
+    T = np.random.default_rng(1).permutation(np.linspace(0.3, 2.0, 200))
+    U = T + np.sqrt(np.pi * w) / 2 * np.array([erf((t - 0.6) / np.sqrt(w)) for t in T])
+    _, _, tg, smax, scold = caloric_slope(T, U, window=5)
+    assert tg == pytest.approx(0.6, abs=0.02)
+    assert smax == pytest.approx(2.0, rel=0.02)
+    assert scold < smax
 
 
-def test_break_needs_points():
+def test_needs_points():
     with pytest.raises(ValueError):
-        caloric_break([1.0, 2.0, 3.0], [1.0, 2.0, 3.0])
+        caloric_slope([1.0, 2.0, 3.0], [1.0, 2.0, 3.0])
