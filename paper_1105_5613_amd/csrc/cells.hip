@@ -247,6 +247,51 @@ __global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ bsum, i
   if (threadIdx.x == 0) bsum[nb] = carry_s;
 }
 
+// Small grids: the whole exclusive scan in one block, chunk by chunk with a
+// running carry (one launch instead of three).
+__global__ __launch_bounds__(1024) void k_scan_single(const int32_t* __restrict__ in,
+                                                      int32_t* __restrict__ out, int32_t n,
+                                                      const DevState* st) {
+  if (!st->any_rebuild) return;
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t carry_s;
+  constexpr int kPer = 8;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int32_t c0 = 0; c0 < n; c0 += 1024 * kPer) {
+    const int32_t base = c0 + threadIdx.x * kPer;
+    int32_t loc[kPer];
+    int32_t s = 0;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int32_t v = base + e < n ? in[base + e] : 0;
+      loc[e] = s;
+      s += v;
+    }
+    int32_t x = s;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int32_t pre = carry_s, tot = 0;
+    for (int q = 0; q < 16; ++q) {
+      if (q < w) pre += wsum[q];
+      tot += wsum[q];
+    }
+    pre += x - s;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e)
+      if (base + e < n) out[base + e] = pre + loc[e];
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry_s;
+}
+
 __global__ void k_scan_add(int32_t* __restrict__ out, const int32_t* __restrict__ bsum,
                            int32_t n, int32_t nb, const DevState* st) {
   if (!st->any_rebuild) return;
@@ -362,6 +407,10 @@ size_t scan_bsum_elems(int32_t ncells) { return (size_t)nblk(ncells, kScanBlock)
 
 void launch_scan(hipStream_t s, int32_t ncells, const int32_t* counts, int32_t* cell_start,
                  int32_t* bsum, const DevState* st) {
+  if (ncells <= 65536) {
+    k_scan_single<<<1, 1024, 0, s>>>(counts, cell_start, ncells, st);
+    return;
+  }
   int32_t nb = (int32_t)nblk(ncells, kScanBlock);
   k_scan_blocks<<<nb, kScanThreads, 0, s>>>(counts, cell_start, bsum, ncells, st);
   k_scan_top<<<1, 1024, 0, s>>>(bsum, nb, st);
