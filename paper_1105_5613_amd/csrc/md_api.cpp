@@ -200,7 +200,8 @@ void run_chain(md_ctx c, hipStream_t s) {
     launch_commit_order(s, c->ntiles, c->tiles, c->rebuild, c->stride, c->pos_tmp, c->vel_tmp,
                         c->id_tmp, c->pos, c->vel, c->id, c->xref);
   else if (c->staged)
-    launch_nlist_tiles(s, c->ncells, c->cell_rep, c->reps, c->rebuild, c->tab, c->cell_start,
+    launch_nlist_tiles(s, c->ncells, c->cell_rep, c->reps, c->rebuild, c->tab, c->p.ntypes,
+                       c->cell_start,
                        c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
                        c->xref, c->nbr16, c->ncount, c->st, c->cell_tile, c->rtiles);
   else

@@ -223,7 +223,7 @@ size_t force_staged_lds_bytes(int32_t lcap);
 int32_t staged_homes_per_group();
 void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const RepDesc* reps, const int32_t* rebuild, const PairTab* tab,
-                        const int32_t* cell_start, int32_t stride, int32_t cap,
+                        int32_t ntypes, const int32_t* cell_start, int32_t stride, int32_t cap,
                         const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
                         int32_t* ncount, DevState* st, const int32_t* cell_tile,

@@ -210,9 +210,19 @@ __device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_
   return cnt;
 }
 
-// cut-off threshold of the pair (home species ta, lane's candidate species)
-__device__ inline double pick_thr(int32_t ta, double t0, double t1, double t2, double t3) {
-  return ta == 0 ? t0 : (ta == 1 ? t1 : (ta == 2 ? t2 : t3));
+// Cut-off threshold of the pair (home species, lane's candidate species).
+// The home's species comes from the high word of its FP64 species value
+// (0.0, 1.0, 2.0, 3.0 have distinct high words), so the choice is scalar
+// arithmetic on the wave-uniform home record; NT = 2 covers the binary mixture
+// with a single select.
+template <int NT>
+__device__ inline double pick_thr(double wa, double t0, double t1, double t2, double t3) {
+  const int32_t hi = __double2hiint(wa);
+  if constexpr (NT == 2) {
+    return hi == 0 ? t0 : t1;
+  } else {
+    return hi == 0 ? t0 : (hi == 0x3ff00000 ? t1 : (hi == 0x40000000 ? t2 : t3));
+  }
 }
 
 // One wave per home cell (nc >= 3): the lanes take the 64 candidates of one
@@ -229,7 +239,7 @@ __device__ inline double pick_thr(int32_t ta, double t0, double t1, double t2, d
 // of the row tile holding the home cell (stage.h) | species << 14 (uint16,
 // staged path); the slot of a candidate is its piece's first slot in that
 // layout plus its offset inside the piece.
-template <int HPI, int BUF, bool TILE>
+template <int HPI, int BUF, bool TILE, int NT>
 __global__ __launch_bounds__(256) void k_nlist_cells(
     int32_t ncells, const int32_t* __restrict__ cell_rep, const RepDesc* __restrict__ reps,
     const int32_t* __restrict__ rebuild, const PairTab* __restrict__ tab,
@@ -359,7 +369,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
           const double4 pa = pos_tmp[i0 + u];
           const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
           const double ra = (ax * ax + ay * ay) + az * az;
-          const double tha = pick_thr((int32_t)pa.w, t0, t1, t2, t3);
+          const double tha = pick_thr<NT>(pa.w, t0, t1, t2, t3);
           hit[u] = (int)valid & (int)(k != i0 + u) & (int)(ra < tha);
           m[u] = __ballot(hit[u]);
         }
@@ -376,7 +386,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
         const double4 pa = pos_tmp[ia];
         const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
         const double ra = (ax * ax + ay * ay) + az * az;
-        const double tha = pick_thr((int32_t)pa.w, t0, t1, t2, t3);
+        const double tha = pick_thr<NT>(pa.w, t0, t1, t2, t3);
         const bool hita = (int)valid & (int)(k != ia) & (int)(ra < tha);
         const uint64_t ma = __ballot(hita);
         int32_t ca = __builtin_amdgcn_readlane(cntv, h);
@@ -432,11 +442,15 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   double4* pos, double* vel, int32_t* id, double* xref, uint32_t* nbr,
                   int32_t* ncount, DevState* st, int32_t ncells, const int32_t* cell_rep,
                   int32_t any_single, int32_t any_multi, float4* pos16) {
-  if (any_multi)
-    k_nlist_cells<kCwHomes, kCwBuf, false>
-        <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(
-            ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp,
-            id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr);
+  if (any_multi) {
+#define KN(NT)                                                                             \
+  k_nlist_cells<kCwHomes, kCwBuf, false, NT>                                               \
+      <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                       \
+          ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, \
+          id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr)
+    if (ntypes <= 2) KN(2); else KN(4);
+#undef KN
+  }
   if (any_single)
     k_nlist<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, tab, ntypes, cell_start, stride, cap,
                                      pos_tmp, vel_tmp, id_tmp, pos, vel, id, xref, nbr, ncount,
@@ -445,14 +459,18 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
 
 void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const RepDesc* reps, const int32_t* rebuild, const PairTab* tab,
-                        const int32_t* cell_start, int32_t stride, int32_t cap,
+                        int32_t ntypes, const int32_t* cell_start, int32_t stride, int32_t cap,
                         const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
                         int32_t* ncount, DevState* st, const int32_t* cell_tile,
                         const RowTile* rtiles) {
-  k_nlist_cells<kCwHomes, kCwBuf, true><<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(
-      ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, id_tmp, pos,
-      vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles);
+#define KT(NT)                                                                                   \
+  k_nlist_cells<kCwHomes, kCwBuf, true, NT>                                                      \
+      <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                             \
+          ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, id_tmp, \
+          pos, vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles)
+  if (ntypes <= 2) KT(2); else KT(4);
+#undef KT
 }
 
 }  // namespace mdk
