@@ -7,9 +7,10 @@
 // seed refined by two Newton-Raphson steps y <- y (3 - r^2 y^2) / 2, the
 // scheme the paper uses on BlueGene/P ("BlueGene specific optimizations").
 // Mixed form: neighbours are gathered as 16-byte FP32 records relative to
-// their build-time cell centre (make_rec16), from which the displacement is
-// formed in FP32 with an absolute error of a few 1e-7 (half the bytes of the
-// FP64 records, so half the cache-line requests); pair arithmetic and the
+// their build-time cell centre (make_rec16); the list entry carries the cell
+// offset d of the pair, so the displacement is (off_i - off_j) + d * side in
+// FP32 (a table lookup by the entry's code), with an absolute error of a few
+// 1e-7; one gather per entry instead of two; pair arithmetic and the
 // per-particle force sum are FP32; per-particle energy/virial are widened to
 // FP64 for the reductions.
 //
@@ -99,9 +100,9 @@ __global__ __launch_bounds__(kTile) void k_force(
   using T = typename std::conditional<MIXED, float, double>::type;
   __shared__ PairLds<T> P;
   __shared__ double s_mass[4];
+  __shared__ float4 s_doff[64];  // mixed: d * cell side for each entry code
   load_pair<T>(P, tab);
   if (threadIdx.x < 4) s_mass[threadIdx.x] = tab->mass[threadIdx.x];
-  __syncthreads();
 
   // with TPP lanes per particle a block covers kTile / TPP particles; a tile
   // of kTile particles takes TPP consecutive (logical) blocks
@@ -110,6 +111,14 @@ __global__ __launch_bounds__(kTile) void k_force(
   const int32_t sub = lb % TPP;
   const Tile t = tiles[tile_id];
   const RepDesc& Rp = reps[t.rep];
+  if (MIXED && threadIdx.x < 64) {
+    const float sf = (float)Rp.cside;
+    const uint32_t c = threadIdx.x << kIdxBits;
+    s_doff[threadIdx.x] = make_float4((float)decode_shift(c, 26) * sf,
+                                      (float)decode_shift(c, 28) * sf,
+                                      (float)decode_shift(c, 30) * sf, 0.0f);
+  }
+  __syncthreads();
   const double L = Rp.L;
   const int32_t lane_p = threadIdx.x % TPP;
   const int32_t i = t.start + sub * (kTile / TPP) + threadIdx.x / TPP;
@@ -135,12 +144,7 @@ __global__ __launch_bounds__(kTile) void k_force(
     if constexpr (MIXED) {
       // 16-byte cell-relative records (see make_rec16)
       const float4 pi = pos16[i];
-      const uint32_t wi = __float_as_uint(pi.w);
-      const int32_t cxi = (int32_t)(wi & 1023u), cyi = (int32_t)((wi >> 10) & 1023u),
-                    czi = (int32_t)((wi >> 20) & 1023u);
-      ti = (int32_t)(wi >> 30);
-      const float sf = (float)Rp.cside, df = (float)Rp.cdelta;
-      const int32_t nc = Rp.nc;
+      ti = (int32_t)(__float_as_uint(pi.w) >> 30);
       for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
         float4 q[U];
 #pragma unroll
@@ -153,24 +157,11 @@ __global__ __launch_bounds__(kTile) void k_force(
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const uint32_t wj = __float_as_uint(q[u].w);
-          int32_t mx = cxi - (int32_t)(wj & 1023u), my = cyi - (int32_t)((wj >> 10) & 1023u),
-                  mz = czi - (int32_t)((wj >> 20) & 1023u);
-          float ddx = pi.x - q[u].x, ddy = pi.y - q[u].y, ddz = pi.z - q[u].z;
-          if (__ballot(e[u] >> kIdxBits)) {  // wave-uniform, as in the FP64 form
-            const int32_t sx = decode_shift(e[u], 26), sy = decode_shift(e[u], 28),
-                          sz = decode_shift(e[u], 30);
-            mx -= sx * nc;
-            my -= sy * nc;
-            mz -= sz * nc;
-            ddx -= (float)sx * df;
-            ddy -= (float)sy * df;
-            ddz -= (float)sz * df;
-          }
-          ddx += (float)mx * sf;
-          ddy += (float)my * sf;
-          ddz += (float)mz * sf;
-          const int32_t ab = ti * 4 + (int32_t)(wj >> 30);
+          // (off_i - off_j) + d * side, d = c_i - c_j - s nc from the entry
+          const float4 dd = s_doff[e[u] >> kIdxBits];
+          const float ddx = (pi.x - q[u].x) + dd.x, ddy = (pi.y - q[u].y) + dd.y,
+                      ddz = (pi.z - q[u].z) + dd.z;
+          const int32_t ab = ti * 4 + (int32_t)(__float_as_uint(q[u].w) >> 30);
           const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
           if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
             const float rinv = __builtin_amdgcn_rsqf(r2);

@@ -426,8 +426,7 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     d.half_skin2 = (0.5 * p->skin) * (0.5 * p->skin);
     d.dof = 3.0 * (double)n[r] - 3.0;
     d.volume = L[r] * L[r] * L[r];
-    d.cside = (double)(float)(L[r] / nc);
-    d.cdelta = L[r] - (double)nc * d.cside;
+    d.cside = L[r] / nc;
     d.off = off;
     d.n = (int32_t)n[r];
     d.coff = coff;

@@ -67,16 +67,18 @@ struct RepDesc {       // per-replica geometry, device resident
   int32_t tile0, tile1;// tiles [tile0, tile1)
   int32_t fb0, fb1;    // force-kernel partial blocks [fb0, fb1) of this replica
   int32_t cb0, cb1;    // reduction chunks [cb0, cb1) (two-level reduction only)
-  double cside;        // cell side rounded to FP32 (exact in both precisions)
-  double cdelta;       // L - nc * cside (periodic-image correction of the mixed form)
+  double cside;        // cell side L / nc
 };
 
 // Mixed form gather record of a particle (16 B): FP32 offsets from the centre
-// of the cell it was binned into at the last list build, (c + 1/2) * cside,
-// and a word holding the cell coordinates (10 bits each) and the species
-// (bits 30-31).  The displacement of a listed pair is then, in FP32,
-//   (off_i - off_j) + (c_i - c_j - s nc) * cside - s * cdelta,
-// with s the periodic image of the entry.
+// of the cell it was binned into at the last list build, (c + 1/2) * cside
+// formed in FP64, and a word holding the cell coordinates (10 bits each,
+// for the record updates of the drift) and the species (bits 30-31).  With
+// s the periodic image of a listed pair, x_i - (x_j + s L) equals
+//   (off_i - off_j) + (c_i - c_j - s nc) * cside
+// exactly; mixed lists carry d = c_i - c_j - s nc in {-1, 0, 1}^3, and the
+// force kernel forms the displacement in FP32 from the records and d * cside
+// rounded to FP32.
 __device__ inline uint32_t pack_cell(int32_t cx, int32_t cy, int32_t cz, int32_t t) {
   return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20) | ((uint32_t)t << 30);
 }

@@ -8,9 +8,13 @@
 //     d = (x_j + s L) - x_i,  r^2 = (dx dx + dy dy) + dz dz  <  (rc_ab + skin)^2
 // so this file is compiled without FMA contraction (also forced below).
 //
-// List entry: sorted index j (26 bits) | periodic image code (6 bits): two
-// bits per axis holding s in {-1, 0, 1} in two's complement, so an entry
-// without a periodic shift is the plain index.
+// List entry: sorted index j (26 bits) | a 6-bit code, two bits per axis in
+// two's complement.  FP64 lists: the periodic image s in {-1, 0, 1} of the
+// partner (x_j + s L), so an entry without a shift is the plain index.
+// Mixed lists: the cell offset d = c_i - c_j - s nc in {-1, 0, 1} between
+// the build-time cells of the pair, which turns the 16-byte cell-relative
+// records into the displacement (off_i - off_j) + d * cell side (see
+// make_rec16) with no further decoding.
 #include "stage.h"
 
 #pragma clang fp contract(off)
@@ -41,14 +45,15 @@ __device__ inline int32_t cell_coord(double c, double inv_cell, int32_t nc) {
   return q > nc - 1 ? nc - 1 : q;
 }
 
+// One-cell boxes (nc = 1): every other particle of the replica is tested
+// with the minimum image  d - L nearbyint(d / L).
 __global__ __launch_bounds__(kTile) void k_nlist(
     const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
-    const int32_t* __restrict__ rebuild, const PairTab* __restrict__ tab, int32_t ntypes,
-    const int32_t* __restrict__ cell_start, int32_t stride, int32_t cap,
-    const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
+    const int32_t* __restrict__ rebuild, const PairTab* __restrict__ tab, int32_t stride,
+    int32_t cap, const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
     const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
     int32_t* __restrict__ id, double* __restrict__ xref, uint32_t* __restrict__ nbr,
-    int32_t* __restrict__ ncount, DevState* st, int32_t skip_multi, float4* __restrict__ pos16) {
+    int32_t* __restrict__ ncount, DevState* st, int32_t dcode, float4* __restrict__ pos16) {
   __shared__ double s_thr[16];
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
@@ -57,101 +62,28 @@ __global__ __launch_bounds__(kTile) void k_nlist(
   const int32_t i = t.start + threadIdx.x;
   if (i >= t.end) return;
   const RepDesc R = reps[t.rep];
-  if (R.nc != 1 && skip_multi) return;  // handled by k_nlist_cells
+  if (R.nc != 1) return;  // cell grids: k_nlist_cells
   const double4 p = pos_tmp[i];
   const int32_t ti = (int32_t)p.w;
   const double* thr = &s_thr[ti * 4];
   int32_t cnt = 0;
   uint32_t* out = nbr + list_base(i, cap);
-  if (R.nc == 1) {
-    // one cell: the minimum image  d - L nearbyint(d / L)
-    for (int32_t j = R.off; j < R.off + R.n; ++j) {
-      if (j == i) continue;
-      const double4 q = pos_tmp[j];
-      double ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
-      double kx = rint(ex / R.L), ky = rint(ey / R.L), kz = rint(ez / R.L);
-      double tx = R.L * kx, ty = R.L * ky, tz = R.L * kz;
-      ex = ex - tx;
-      ey = ey - ty;
-      ez = ez - tz;
-      double r2 = (ex * ex + ey * ey) + ez * ez;
-      if (r2 < thr[(int32_t)q.w]) {
-        if (cnt < cap)
-          out[(size_t)cnt * kSlice] =
-              (uint32_t)j | image_code(-(int32_t)kx, -(int32_t)ky, -(int32_t)kz);
-        ++cnt;
-      }
-    }
-  } else {
-    // 9 neighbour rows; along x the cells cx-1 .. cx+1 of a row are one
-    // contiguous range unless the row wraps, then up to three ranges
-    const int32_t nc = R.nc;
-    const int32_t qx = cell_coord(p.x, R.inv_cell, nc);
-    const int32_t qy = cell_coord(p.y, R.inv_cell, nc);
-    const int32_t qz = cell_coord(p.z, R.inv_cell, nc);
-    for (int32_t oz = -1; oz <= 1; ++oz) {
-      int32_t nz, sz;
-      stencil_axis(qz, oz, nc, nz, sz);
-      const double shz = (double)sz * R.L;
-      for (int32_t oy = -1; oy <= 1; ++oy) {
-        int32_t ny, sy;
-        stencil_axis(qy, oy, nc, ny, sy);
-        const double shy = (double)sy * R.L;
-        const int32_t rowbase = R.coff + (nz * nc + ny) * nc;
-        int32_t r0[3], r1[3], rs[3];
-        int nr = 0;
-        if (qx - 1 < 0) {
-          r0[nr] = cell_start[rowbase + nc - 1];
-          r1[nr] = cell_start[rowbase + nc];
-          rs[nr++] = -1;
-        }
-        {
-          const int32_t lo = qx - 1 < 0 ? 0 : qx - 1;
-          const int32_t hi = qx + 1 >= nc ? nc - 1 : qx + 1;
-          r0[nr] = cell_start[rowbase + lo];
-          r1[nr] = cell_start[rowbase + hi + 1];
-          rs[nr++] = 0;
-        }
-        if (qx + 1 >= nc) {
-          r0[nr] = cell_start[rowbase];
-          r1[nr] = cell_start[rowbase + 1];
-          rs[nr++] = 1;
-        }
-        for (int m = 0; m < nr; ++m) {
-          const double shx = (double)rs[m] * R.L;
-          const uint32_t code = image_code(rs[m], sy, sz);
-          int32_t k = r0[m];
-          const int32_t k1 = r1[m];
-          // four candidates per iteration keep four gathers in flight
-          for (; k + 4 <= k1; k += 4) {
-            double4 q[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) q[u] = pos_tmp[k + u];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const double ex = (q[u].x + shx) - p.x;
-              const double ey = (q[u].y + shy) - p.y;
-              const double ez = (q[u].z + shz) - p.z;
-              const double r2 = (ex * ex + ey * ey) + ez * ez;
-              if (k + u != i && r2 < thr[(int32_t)q[u].w]) {
-                if (cnt < cap) out[(size_t)cnt * kSlice] = (uint32_t)(k + u) | code;
-                ++cnt;
-              }
-            }
-          }
-          for (; k < k1; ++k) {
-            const double4 q = pos_tmp[k];
-            const double ex = (q.x + shx) - p.x;
-            const double ey = (q.y + shy) - p.y;
-            const double ez = (q.z + shz) - p.z;
-            const double r2 = (ex * ex + ey * ey) + ez * ez;
-            if (k != i && r2 < thr[(int32_t)q.w]) {
-              if (cnt < cap) out[(size_t)cnt * kSlice] = (uint32_t)k | code;
-              ++cnt;
-            }
-          }
-        }
-      }
+  for (int32_t j = R.off; j < R.off + R.n; ++j) {
+    if (j == i) continue;
+    const double4 q = pos_tmp[j];
+    double ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
+    double kx = rint(ex / R.L), ky = rint(ey / R.L), kz = rint(ez / R.L);
+    double tx = R.L * kx, ty = R.L * ky, tz = R.L * kz;
+    ex = ex - tx;
+    ey = ey - ty;
+    ez = ez - tz;
+    double r2 = (ex * ex + ey * ey) + ez * ez;
+    if (r2 < thr[(int32_t)q.w]) {
+      // image s = -k; with one cell d = -s nc = k
+      const int32_t sx = -(int32_t)kx, sy = -(int32_t)ky, sz = -(int32_t)kz;
+      const uint32_t code = dcode ? image_code(-sx, -sy, -sz) : image_code(sx, sy, sz);
+      if (cnt < cap) out[(size_t)cnt * kSlice] = (uint32_t)j | code;
+      ++cnt;
     }
   }
   ncount[i] = cnt;
@@ -170,7 +102,6 @@ __global__ __launch_bounds__(kTile) void k_nlist(
   vel[stride + i] = vel_tmp[stride + i];
   vel[2 * (size_t)stride + i] = vel_tmp[2 * (size_t)stride + i];
   id[i] = id_tmp[i];
-  (void)ntypes;
 }
 
 
@@ -249,7 +180,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
     int32_t* __restrict__ id, double* __restrict__ xref,
     typename std::conditional<TILE, uint16_t, uint32_t>::type* __restrict__ nbr,
     int32_t* __restrict__ ncount, DevState* st, float4* __restrict__ pos16,
-    const int32_t* __restrict__ cell_tile, const RowTile* __restrict__ rtiles) {
+    const int32_t* __restrict__ cell_tile, const RowTile* __restrict__ rtiles, int32_t dcode) {
   using E = typename std::conditional<TILE, uint16_t, uint32_t>::type;
   __shared__ double s_thr[16];
   __shared__ int32_t s_pre[4][28];    // first packed candidate of piece p
@@ -354,10 +285,17 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
       const int32_t tj = (int32_t)q.w;  // thr[4 ta + tj] is the pair (ta, tj)
       const double t0 = s_thr[tj], t1 = s_thr[4 + tj], t2 = s_thr[8 + tj], t3 = s_thr[12 + tj];
       uint32_t entry;
-      if constexpr (TILE)
+      if constexpr (TILE) {
         entry = (uint32_t)((s_l0[w][p] + (v - s_pre[w][p])) & 0x3fff) | ((uint32_t)tj << 14);
-      else
+      } else if (dcode) {
+        // d = c_i - c_j - s nc: -dy, -dz of the row; along x from the
+        // partner's build-time cell and the piece's shift
+        const int32_t row = p / 3, kind = p - 3 * row;
+        const int32_t cxj = cell_coord(q.x, R.inv_cell, nc);
+        entry = (uint32_t)k | image_code(qx - cxj - (kind - 1) * nc, 1 - row % 3, 1 - row / 3);
+      } else {
         entry = (uint32_t)k | code;
+      }
       int32_t h = 0;
       // HPI home particles per iteration (wave-uniform, scalar loads)
       for (; h + HPI <= gn; h += HPI) {
@@ -442,19 +380,20 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   double4* pos, double* vel, int32_t* id, double* xref, uint32_t* nbr,
                   int32_t* ncount, DevState* st, int32_t ncells, const int32_t* cell_rep,
                   int32_t any_single, int32_t any_multi, float4* pos16) {
+  // mixed lists (records present) carry cell offsets instead of images
+  const int32_t dcode = pos16 != nullptr;
   if (any_multi) {
 #define KN(NT)                                                                             \
   k_nlist_cells<kCwHomes, kCwBuf, false, NT>                                               \
       <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                       \
           ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, \
-          id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr)
+          id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr, dcode)
     if (ntypes <= 2) KN(2); else KN(4);
 #undef KN
   }
   if (any_single)
-    k_nlist<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, tab, ntypes, cell_start, stride, cap,
-                                     pos_tmp, vel_tmp, id_tmp, pos, vel, id, xref, nbr, ncount,
-                                     st, 1, pos16);
+    k_nlist<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, tab, stride, cap, pos_tmp, vel_tmp,
+                                     id_tmp, pos, vel, id, xref, nbr, ncount, st, dcode, pos16);
 }
 
 void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
@@ -468,7 +407,7 @@ void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
   k_nlist_cells<kCwHomes, kCwBuf, true, NT>                                                      \
       <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                             \
           ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, id_tmp, \
-          pos, vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles)
+          pos, vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles, 0)
   if (ntypes <= 2) KT(2); else KT(4);
 #undef KT
 }
