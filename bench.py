@@ -258,7 +258,7 @@ def main():
     ap.add_argument("--commands", default="")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: there is no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     sys.path.insert(0, ROOT)

@@ -300,22 +300,22 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
       // HPI home particles per iteration (wave-uniform, scalar loads)
       for (; h + HPI <= gn; h += HPI) {
         const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
-        bool hit[HPI];
-        uint64_t m[HPI];
+        // the distances of HPI homes first (independent work), then the
+        // tests, ballots and appends home by home
+        double ra[HPI], tha[HPI];
 #pragma unroll
         for (int u = 0; u < HPI; ++u) {
           const double4 pa = pos_tmp[i0 + u];
           const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
-          const double ra = (ax * ax + ay * ay) + az * az;
-          const double tha = pick_thr<NT>(pa.w, t0, t1, t2, t3);
-          hit[u] = (int)valid & (int)(k != i0 + u) & (int)(ra < tha);
-          m[u] = __ballot(hit[u]);
+          ra[u] = (ax * ax + ay * ay) + az * az;
+          tha[u] = pick_thr<NT>(pa.w, t0, t1, t2, t3);
         }
 #pragma unroll
         for (int u = 0; u < HPI; ++u) {
+          const bool hit = valid && k != i0 + u && ra[u] < tha[u];
+          const uint64_t m = __ballot(hit);
           int32_t cu = __builtin_amdgcn_readlane(cntv, h + u);
-          cu = cw_append(m[u], hit[u], cu, h + u, i0 + u, entry, cap, rows_lds, gn, stride, buf,
-                         nbr);
+          cu = cw_append(m, hit, cu, h + u, i0 + u, entry, cap, rows_lds, gn, stride, buf, nbr);
           cntv = lane == h + u ? cu : cntv;
         }
       }
