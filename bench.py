@@ -239,7 +239,7 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed,large,batched,cells,soft")
     ap.add_argument("--profile-every", type=int, default=4,
                     help="bracket the force launch of every k-th timed step with hipEvents")
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--replicas", type=int, default=256)
