@@ -193,7 +193,9 @@ md_status md_replica_info(md_ctx ctx, int32_t rep, int32_t* nc, double* inv_cell
 /* Kernel timing (not part of the method; for roofline measurement).
  * md_profile(ctx, every): from now on, in md_step the force kernel launch of
  * every `every`-th step (0 = off) is bracketed by two hipEvents recorded on
- * the context stream; earlier records are discarded.
+ * the context stream; earlier records are discarded.  While profiling is on,
+ * md_step launches every step directly (graph_steps is ignored: events
+ * recorded by a replayed graph cannot be timed).
  * md_profile_read: synchronises and returns the number of bracketed force
  * launches and their summed duration in milliseconds. */
 typedef struct {

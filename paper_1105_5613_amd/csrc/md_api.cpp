@@ -33,6 +33,7 @@ struct md_ctx_s {
   RepDesc* reps = nullptr;
   Tile* tiles = nullptr;
   PairTab* tab = nullptr;
+  int32_t thr_form = 4;  // list threshold form of the neighbour search (list_thr_form)
   DevState* st = nullptr;
   int32_t *cell_rep = nullptr, *counts = nullptr, *cell_start = nullptr, *bsum = nullptr;
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp_src = nullptr;
@@ -200,12 +201,12 @@ void run_chain(md_ctx c, hipStream_t s) {
     launch_commit_order(s, c->ntiles, c->tiles, c->rebuild, c->stride, c->pos_tmp, c->vel_tmp,
                         c->id_tmp, c->pos, c->vel, c->id, c->xref);
   else if (c->staged)
-    launch_nlist_tiles(s, c->ncells, c->cell_rep, c->reps, c->rebuild, c->tab, c->p.ntypes,
+    launch_nlist_tiles(s, c->ncells, c->cell_rep, c->reps, c->rebuild, c->tab, c->thr_form,
                        c->cell_start,
                        c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
                        c->xref, c->nbr16, c->ncount, c->st, c->cell_tile, c->rtiles);
   else
-    launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->p.ntypes, c->cell_start,
+    launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->thr_form, c->cell_start,
                  c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
                  c->xref, c->nbr, c->ncount, c->st, c->ncells, c->cell_rep, c->any_single,
                  c->any_multi, c->pos16);
@@ -566,6 +567,7 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
     tab.mass[a] = a < p->ntypes ? p->mass[a] : 1.0;
     tab.inv_mass[a] = 1.0 / tab.mass[a];
   }
+  c->thr_form = list_thr_form(tab, p->ntypes);
 
   std::vector<int32_t> cell_rep(c->ncells);
   for (int r = 0; r < nrep; ++r) {
@@ -789,7 +791,9 @@ md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
   hipStream_t s = c->stream;
   launch_begin_call(s, c->nrep, c->kcall, c->lam);
   int32_t k = 0;
-  const int32_t K = c->p.graph_steps;
+  // events recorded inside a captured graph cannot be timed, so profiled
+  // steps are launched directly
+  const int32_t K = c->prof_every > 0 ? 0 : c->p.graph_steps;
   if (K > 0 && nsteps >= K) {
     md_status rc = ensure_graph(c, ta, thermo, K);
     if (rc) return rc;

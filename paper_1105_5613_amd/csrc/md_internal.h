@@ -149,9 +149,12 @@ void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* tmp_src, int32_t stride, const int32_t* id,
                         const double4* pos, const double* vel, int32_t* id_tmp,
                         double4* pos_tmp, double* vel_tmp);
-// nlist.hip
+// nlist.hip.  thr_form = 2: every pair threshold of the list test is formed
+// as thr[0][b] + (thr[1][b] - thr[0][b]) * species_a in one FMA, exact when
+// list_thr_form() says so; 4: a select chain over up to four species.
+int32_t list_thr_form(const PairTab& tab, int32_t ntypes);
 void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
-                  const int32_t* rebuild, const PairTab* tab, int32_t ntypes,
+                  const int32_t* rebuild, const PairTab* tab, int32_t thr_form,
                   const int32_t* cell_start, int32_t stride, int32_t cap,
                   const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                   double4* pos, double* vel, int32_t* id, double* xref,
@@ -225,7 +228,7 @@ size_t force_staged_lds_bytes(int32_t lcap);
 int32_t staged_homes_per_group();
 void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const RepDesc* reps, const int32_t* rebuild, const PairTab* tab,
-                        int32_t ntypes, const int32_t* cell_start, int32_t stride, int32_t cap,
+                        int32_t thr_form, const int32_t* cell_start, int32_t stride, int32_t cap,
                         const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
                         int32_t* ncount, DevState* st, const int32_t* cell_tile,

@@ -116,6 +116,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
 constexpr int kCwGroup = 64;  // home particles per pass: lane h keeps the count of home h
 constexpr int kCwHomes = 4;   // home particles tested per iteration
 constexpr int kCwBuf = 1024;  // list entries staged in LDS per wave (4 KB)
+constexpr double kFar = 1.0e300;  // x of the idle lanes of a chunk: r^2 overflows to +inf
 
 // Append the hits of the lane's candidate for home particle hl of the group
 // (wave-uniform) at that particle's running count cnt.  Rows below rows_lds
@@ -141,17 +142,20 @@ __device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_
   return cnt;
 }
 
-// Cut-off threshold of the pair (home species, lane's candidate species).
-// The home's species comes from the high word of its FP64 species value
-// (0.0, 1.0, 2.0, 3.0 have distinct high words), so the choice is scalar
-// arithmetic on the wave-uniform home record; NT = 2 covers the binary mixture
-// with a single select.
+// Cut-off threshold of the pair (home species a, lane's candidate species b),
+// with the home's species value wa (0.0, 1.0, ...) wave-uniform.
+// NT = 2: thr = t0 + (t1 - t0) wa as one fused multiply-add.  The launch picks
+// this form only when t1 / 2 <= t0 <= 2 t1 for every b, so d = t1 - t0 is
+// exact (Sterbenz) and fma(d, 1, t0) = t1, fma(d, 0, t0) = t0 are the
+// tabulated values bit for bit.  NT = 4: a select chain on the high word of
+// wa (0.0, 1.0, 2.0, 3.0 have distinct high words).
 template <int NT>
-__device__ inline double pick_thr(double wa, double t0, double t1, double t2, double t3) {
-  const int32_t hi = __double2hiint(wa);
+__device__ inline double pick_thr(double wa, double t0, double d, double t1, double t2,
+                                  double t3) {
   if constexpr (NT == 2) {
-    return hi == 0 ? t0 : t1;
+    return __builtin_fma(d, wa, t0);
   } else {
+    const int32_t hi = __double2hiint(wa);
     return hi == 0 ? t0 : (hi == 0x3ff00000 ? t1 : (hi == 0x40000000 ? t2 : t3));
   }
 }
@@ -277,13 +281,15 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
       const int32_t k = valid ? s_k0[w][p] + (v - s_pre[w][p]) : h0;
       const uint32_t code = (uint32_t)s_code[w][p];
       const double4 q = pos_tmp[k];
-      // the periodic shift of the piece: x_j + s L
+      // the periodic shift of the piece: x_j + s L; lanes past the last
+      // candidate sit far away, so their test fails without a mask
       const double sx = (double)(((int32_t)(code << 4)) >> 30) * R.L;
       const double sy = (double)(((int32_t)(code << 2)) >> 30) * R.L;
       const double sz = (double)(((int32_t)code) >> 30) * R.L;
-      const double xs = q.x + sx, ys = q.y + sy, zs = q.z + sz;
+      const double xs = valid ? q.x + sx : kFar, ys = q.y + sy, zs = q.z + sz;
       const int32_t tj = (int32_t)q.w;  // thr[4 ta + tj] is the pair (ta, tj)
       const double t0 = s_thr[tj], t1 = s_thr[4 + tj], t2 = s_thr[8 + tj], t3 = s_thr[12 + tj];
+      const double d01 = t1 - t0;
       uint32_t entry;
       if constexpr (TILE) {
         entry = (uint32_t)((s_l0[w][p] + (v - s_pre[w][p])) & 0x3fff) | ((uint32_t)tj << 14);
@@ -296,37 +302,49 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
       } else {
         entry = (uint32_t)k | code;
       }
+      // the cell's own particles -- the only candidates that can be the home
+      // particle itself -- are the main piece of the central row; chunks that
+      // miss them skip the self test
+      const int32_t sv0 = s_pre[w][13] + (h0 - s_k0[w][13]);
+      const bool self_chunk = base < sv0 + nh && sv0 < base + 64;
       int32_t h = 0;
-      // HPI home particles per iteration (wave-uniform, scalar loads)
-      for (; h + HPI <= gn; h += HPI) {
-        const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
-        // the distances of HPI homes first (independent work), then the
-        // tests, ballots and appends home by home
-        double ra[HPI], tha[HPI];
+      // HPI home particles per iteration (wave-uniform, scalar loads): the
+      // distances first (independent work), then test, ballot and append
+      // home by home
+      auto homes = [&](auto self_tag) {
+        constexpr bool SELF = decltype(self_tag)::value;
+        for (; h + HPI <= gn; h += HPI) {
+          const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
+          double ra[HPI], tha[HPI];
 #pragma unroll
-        for (int u = 0; u < HPI; ++u) {
-          const double4 pa = pos_tmp[i0 + u];
-          const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
-          ra[u] = (ax * ax + ay * ay) + az * az;
-          tha[u] = pick_thr<NT>(pa.w, t0, t1, t2, t3);
-        }
+          for (int u = 0; u < HPI; ++u) {
+            const double4 pa = pos_tmp[i0 + u];
+            const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
+            ra[u] = (ax * ax + ay * ay) + az * az;
+            tha[u] = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
+          }
 #pragma unroll
-        for (int u = 0; u < HPI; ++u) {
-          const bool hit = valid && k != i0 + u && ra[u] < tha[u];
-          const uint64_t m = __ballot(hit);
-          int32_t cu = __builtin_amdgcn_readlane(cntv, h + u);
-          cu = cw_append(m, hit, cu, h + u, i0 + u, entry, cap, rows_lds, gn, stride, buf, nbr);
-          cntv = lane == h + u ? cu : cntv;
+          for (int u = 0; u < HPI; ++u) {
+            const bool hit = SELF ? (k != i0 + u && ra[u] < tha[u]) : ra[u] < tha[u];
+            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+            int32_t cu = __builtin_amdgcn_readlane(cntv, h + u);
+            cu = cw_append(m, hit, cu, h + u, i0 + u, entry, cap, rows_lds, gn, stride, buf, nbr);
+            cntv = lane == h + u ? cu : cntv;
+          }
         }
-      }
+      };
+      if (self_chunk)
+        homes(std::true_type{});
+      else
+        homes(std::false_type{});
       for (; h < gn; ++h) {
         const int32_t ia = __builtin_amdgcn_readfirstlane(gbase + h);
         const double4 pa = pos_tmp[ia];
         const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
         const double ra = (ax * ax + ay * ay) + az * az;
-        const double tha = pick_thr<NT>(pa.w, t0, t1, t2, t3);
-        const bool hita = (int)valid & (int)(k != ia) & (int)(ra < tha);
-        const uint64_t ma = __ballot(hita);
+        const double tha = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
+        const bool hita = k != ia && ra < tha;
+        const uint64_t ma = __builtin_amdgcn_ballot_w64(hita);
         int32_t ca = __builtin_amdgcn_readlane(cntv, h);
         ca = cw_append(ma, hita, ca, h, ia, entry, cap, rows_lds, gn, stride, buf, nbr);
         cntv = lane == h ? ca : cntv;
@@ -373,8 +391,18 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
 
 }  // namespace
 
+int32_t list_thr_form(const PairTab& tab, int32_t ntypes) {
+  if (ntypes == 1) return 2;  // species 0 only: fma(d, 0, t0) = t0 for any finite d
+  if (ntypes > 2) return 4;
+  for (int b = 0; b < 2; ++b) {
+    const double t0 = tab.thr[b], t1 = tab.thr[4 + b];
+    if (!(t0 * 0.5 <= t1 && t1 <= 2.0 * t0)) return 4;  // t1 - t0 might round
+  }
+  return 2;
+}
+
 void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
-                  const int32_t* rebuild, const PairTab* tab, int32_t ntypes,
+                  const int32_t* rebuild, const PairTab* tab, int32_t thr_form,
                   const int32_t* cell_start, int32_t stride, int32_t cap,
                   const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                   double4* pos, double* vel, int32_t* id, double* xref, uint32_t* nbr,
@@ -388,7 +416,7 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
       <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                       \
           ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, \
           id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr, dcode)
-    if (ntypes <= 2) KN(2); else KN(4);
+    if (thr_form == 2) KN(2); else KN(4);
 #undef KN
   }
   if (any_single)
@@ -398,7 +426,7 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
 
 void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const RepDesc* reps, const int32_t* rebuild, const PairTab* tab,
-                        int32_t ntypes, const int32_t* cell_start, int32_t stride, int32_t cap,
+                        int32_t thr_form, const int32_t* cell_start, int32_t stride, int32_t cap,
                         const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
                         int32_t* ncount, DevState* st, const int32_t* cell_tile,
@@ -408,7 +436,7 @@ void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
       <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                             \
           ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, id_tmp, \
           pos, vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles, 0)
-  if (ntypes <= 2) KT(2); else KT(4);
+  if (thr_form == 2) KT(2); else KT(4);
 #undef KT
 }
 

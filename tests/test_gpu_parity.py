@@ -84,6 +84,50 @@ def test_cells_lists_forces_fp64(torch_cuda, n, seed, kw):
     assert ob["n_rebuild"] == 1
 
 
+# Species tables beyond the binary mixture.  The list test forms the pair
+# threshold either as one FMA over the home species value (one species, or two
+# whose thresholds for each partner species lie within a factor of two) or by
+# a select chain: "one" takes the first form, "two-wide" and "three" the second.
+SPECIES_TABLES = {
+    "one": ([[1.0]], [[1.0]], [[2.5]], [1.0]),
+    "two-wide": ([[1.0, 1.5], [1.5, 0.5]], [[1.0, 0.7], [0.7, 0.4]],
+                 [[2.5, 1.75], [1.75, 1.0]], [1.0, 0.5]),
+    "three": ([[1.0, 1.2, 0.8], [1.2, 0.6, 1.0], [0.8, 1.0, 0.9]],
+              [[1.0, 0.9, 0.8], [0.9, 0.85, 0.75], [0.8, 0.75, 0.7]],
+              [[2.5, 2.25, 2.0], [2.25, 2.125, 1.875], [2.0, 1.875, 1.75]], [1.0, 0.9, 0.8]),
+}
+
+
+@pytest.mark.parametrize("name,precision,path", [
+    ("one", 0, 1), ("two-wide", 0, 1), ("two-wide", 0, 2), ("three", 0, 1), ("three", 0, 2),
+    ("three", 1, 1)])
+def test_species_tables(torch_cuda, name, precision, path):
+    from paper_1105_5613_amd import System, make_params
+    say(f"case species table {name} precision={precision} path={path}")
+    eps, sig, rc, mass = SPECIES_TABLES[name]
+    n = 13500
+    s = initconf.fcc_system(n, seed=21, temperature=1.0)
+    nt = len(eps)
+    types = np.random.default_rng(22).integers(0, nt, n).astype(np.int32) if nt != 2 \
+        else s["type"]
+    sysm = System(make_params(eps, sig, rc, mass, skin=0.3, precision=precision, path=path),
+                  [n], [s["L"]])
+    sysm.set_state(s["x"], s["v"], types)
+    p = oracle.make_params(eps, sig, rc, mass, skin=0.3)
+    sysm.build_cells()
+    xw, count, ids = compare_cells_lists(sysm, p, s["x"], types, s["L"], tag=name)
+    sysm.forces()
+    F = sysm.get_forces().cpu().numpy()
+    Fo, peo, wo = oracle.forces_list(p, xw, types, s["L"], count, ids)
+    e = floored_err(F, Fo)
+    say(f"  force error {e:.3e}")
+    assert e <= (1e-12 if precision == 0 else 1e-5)
+    ob = sysm.observables()[0]
+    rel = 1e-12 if precision == 0 else 1e-6
+    assert ob["pe"] == pytest.approx(peo, rel=rel)
+    assert ob["virial"] == pytest.approx(wo, rel=rel)
+
+
 @pytest.mark.parametrize("path", ["gather", "staged"])
 def test_forces_mixed(torch_cuda, path):
     say(f"case forces mixed n=32000 {path}")
