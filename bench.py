@@ -78,21 +78,18 @@ def mixture():
 
 
 def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int,
-               path: int = 1, potential: int = 0, global_rc=None, dt: float = 0.005, T0=None,
-               graph_steps: int = 0):
+               path: int = 1, potential: int = 0, global_rc=None, dt: float = 0.005, T0=None):
     from paper_1105_5613_amd import System, make_params
     import initconf
     eps, sig, rc, mass = initconf.mixture_tables(global_rc=global_rc)
     p = make_params(eps, sig, rc, mass, skin=0.3, dt=dt, precision=precision, path=path,
-                    potential=potential, graph_steps=graph_steps)
+                    potential=potential)
     n = inputs["n"]
     sysm = System(p, [n], [inputs["L"]])
     sysm.set_state(inputs["x"], inputs["v"], inputs["type"])
     sysm.step(warmup, T0=T0)
     tuned = sysm.autotune(reps=3)
     sysm.profile(prof_every)
-    if graph_steps:
-        sysm.step(graph_steps, T0=T0)  # captures the graph (with the profiling events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sysm.step(steps, T0=T0)
@@ -252,8 +249,6 @@ def main():
     ap.add_argument("--serial-steps", type=int, default=50)
     ap.add_argument("--graph-steps", type=int, default=100,
                     help="steps per captured hipGraph in the batched form (0: direct launches)")
-    ap.add_argument("--single-graph-steps", type=int, default=0,
-                    help="steps per captured hipGraph in the single-box forms (0: direct launches)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--counters-summary", action="store_true")
     ap.add_argument("--fetch-dir")
@@ -288,7 +283,7 @@ def main():
             continue
         log(f"timing form {f}: {args.steps} steps after {args.warmup} warmup")
         res[f] = run_single(torch, 1 if f == "mixed" else 0, inputs, args.steps, args.warmup,
-                            args.profile_every, graph_steps=args.single_graph_steps)
+                            args.profile_every)
         log(f"  {f}: {res[f]['rate']:.4e} particle-steps/s, {res[f]['ms_per_step']:.4f} ms/step, "
             f"force {res[f]['force_ms_avg']:.4f} ms, nbar {res[f]['nbar']:.2f}, "
             f"rebuilds {res[f]['rebuilds']}")

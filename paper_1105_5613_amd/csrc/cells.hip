@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
                                                int32_t* __restrict__ counts,
                                                int32_t* __restrict__ cell_of,
                                                int32_t* __restrict__ slot, DevState* st) {
+  if (!st->any_rebuild) return;  // one flag load when nothing rebuilds
   const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   if (!rebuild[t.rep]) return;
   const int lane = threadIdx.x & 63;
@@ -305,7 +306,9 @@ __global__ __launch_bounds__(kTile) void k_scatter(const Tile* __restrict__ tile
                                                    const int32_t* __restrict__ cell_of,
                                                    const int32_t* __restrict__ slot,
                                                    const int32_t* __restrict__ cell_start,
-                                                   int32_t* __restrict__ tmp_src) {
+                                                   int32_t* __restrict__ tmp_src,
+                                                   const DevState* __restrict__ st) {
+  if (!st->any_rebuild) return;
   const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   if (!rebuild[t.rep]) return;
   const int32_t i = t.start + threadIdx.x;
@@ -320,7 +323,8 @@ __global__ __launch_bounds__(256) void k_cell_gather(
     const int32_t* __restrict__ cell_start, const int32_t* __restrict__ tmp_src, int32_t stride,
     const int32_t* __restrict__ id, const double4* __restrict__ pos,
     const double* __restrict__ vel, int32_t* __restrict__ id_tmp, double4* __restrict__ pos_tmp,
-    double* __restrict__ vel_tmp) {
+    double* __restrict__ vel_tmp, const DevState* __restrict__ st) {
+  if (!st->any_rebuild) return;
   const int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= ncells) return;
@@ -419,17 +423,18 @@ void launch_scan(hipStream_t s, int32_t ncells, const int32_t* counts, int32_t* 
 
 void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int32_t* rebuild,
                     const int32_t* cell_of, const int32_t* slot, const int32_t* cell_start,
-                    int32_t* tmp_src) {
-  k_scatter<<<ntiles, kTile, 0, s>>>(tiles, rebuild, cell_of, slot, cell_start, tmp_src);
+                    int32_t* tmp_src, const DevState* st) {
+  k_scatter<<<ntiles, kTile, 0, s>>>(tiles, rebuild, cell_of, slot, cell_start, tmp_src, st);
 }
 
 void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* rebuild, const int32_t* cell_start,
                         const int32_t* tmp_src, int32_t stride, const int32_t* id,
                         const double4* pos, const double* vel, int32_t* id_tmp,
-                        double4* pos_tmp, double* vel_tmp) {
+                        double4* pos_tmp, double* vel_tmp, const DevState* st) {
   k_cell_gather<<<nblk(ncells, 4), 256, 0, s>>>(ncells, cell_rep, rebuild, cell_start, tmp_src,
-                                                stride, id, pos, vel, id_tmp, pos_tmp, vel_tmp);
+                                                stride, id, pos, vel, id_tmp, pos_tmp, vel_tmp,
+                                                st);
 }
 
 }  // namespace mdk

@@ -246,7 +246,8 @@ __global__ __launch_bounds__(kTile) void k_commit_order(
     const Tile* __restrict__ tiles, const int32_t* __restrict__ rebuild, int32_t stride,
     const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
     const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
-    int32_t* __restrict__ id, double* __restrict__ xref) {
+    int32_t* __restrict__ id, double* __restrict__ xref, const DevState* __restrict__ st) {
+  if (!st->any_rebuild) return;
   const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   if (!rebuild[t.rep]) return;
   const int32_t i = t.start + threadIdx.x;
@@ -284,9 +285,9 @@ void launch_force_cells(hipStream_t s, int32_t mixed, int32_t mode, int32_t nrt,
 void launch_commit_order(hipStream_t s, int32_t ntiles, const Tile* tiles,
                          const int32_t* rebuild, int32_t stride, const double4* pos_tmp,
                          const double* vel_tmp, const int32_t* id_tmp, double4* pos,
-                         double* vel, int32_t* id, double* xref) {
+                         double* vel, int32_t* id, double* xref, const DevState* st) {
   k_commit_order<<<ntiles, kTile, 0, s>>>(tiles, rebuild, stride, pos_tmp, vel_tmp, id_tmp, pos,
-                                          vel, id, xref);
+                                          vel, id, xref, st);
 }
 
 }  // namespace mdk

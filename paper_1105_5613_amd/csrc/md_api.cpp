@@ -194,12 +194,12 @@ void run_chain(md_ctx c, hipStream_t s) {
              c->cell_of, c->slot, c->st);
   launch_scan(s, c->ncells, c->counts, c->cell_start, c->bsum, c->st);
   launch_scatter(s, c->ntiles, c->tiles, c->rebuild, c->cell_of, c->slot, c->cell_start,
-                 c->tmp_src);
+                 c->tmp_src, c->st);
   launch_cell_gather(s, c->ncells, c->cell_rep, c->rebuild, c->cell_start, c->tmp_src, c->stride,
-                     c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp);
+                     c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp, c->st);
   if (c->cells)
     launch_commit_order(s, c->ntiles, c->tiles, c->rebuild, c->stride, c->pos_tmp, c->vel_tmp,
-                        c->id_tmp, c->pos, c->vel, c->id, c->xref);
+                        c->id_tmp, c->pos, c->vel, c->id, c->xref, c->st);
   else if (c->staged)
     launch_nlist_tiles(s, c->ncells, c->cell_rep, c->reps, c->rebuild, c->tab, c->thr_form,
                        c->cell_start,

@@ -143,12 +143,12 @@ void launch_scan(hipStream_t s, int32_t ncells, const int32_t* counts, int32_t* 
 size_t scan_bsum_elems(int32_t ncells);
 void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int32_t* rebuild,
                     const int32_t* cell_of, const int32_t* slot, const int32_t* cell_start,
-                    int32_t* tmp_src);
+                    int32_t* tmp_src, const DevState* st);
 void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* rebuild, const int32_t* cell_start,
                         const int32_t* tmp_src, int32_t stride, const int32_t* id,
                         const double4* pos, const double* vel, int32_t* id_tmp,
-                        double4* pos_tmp, double* vel_tmp);
+                        double4* pos_tmp, double* vel_tmp, const DevState* st);
 // nlist.hip.  thr_form = 2: every pair threshold of the list test is formed
 // as thr[0][b] + (thr[1][b] - thr[0][b]) * species_a in one FMA, exact when
 // list_thr_form() says so; 4: a select chain over up to four species.
@@ -245,7 +245,7 @@ void launch_force_cells(hipStream_t s, int32_t mixed, int32_t mode, int32_t nrt,
 void launch_commit_order(hipStream_t s, int32_t ntiles, const Tile* tiles,
                          const int32_t* rebuild, int32_t stride, const double4* pos_tmp,
                          const double* vel_tmp, const int32_t* id_tmp, double4* pos,
-                         double* vel, int32_t* id, double* xref);
+                         double* vel, int32_t* id, double* xref, const DevState* st);
 void launch_force_staged(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
                          int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
                          const PairTab* tab, const int32_t* cell_start, const double4* pos,

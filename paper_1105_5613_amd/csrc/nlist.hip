@@ -55,6 +55,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
     int32_t* __restrict__ id, double* __restrict__ xref, uint32_t* __restrict__ nbr,
     int32_t* __restrict__ ncount, DevState* st, int32_t dcode, float4* __restrict__ pos16) {
   __shared__ double s_thr[16];
+  if (!st->any_rebuild) return;
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
   const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   __shared__ int32_t s_l0[4][27];     // TILE: first LDS slot of piece p in the tile layout
   __shared__ int32_t s_rowsz[4][9];   // TILE: slots of tile row q
   extern __shared__ uint32_t s_list[];  // [4][kCwBuf]
+  if (!st->any_rebuild) return;  // whole block: one flag load when nothing rebuilds
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
