@@ -77,6 +77,17 @@ def mixture():
     return initconf.mixture_tables()
 
 
+LOG_EVERY = 10  # observables logged every 10 timed steps (energy drift)
+
+
+def energy_drift(E, n: int) -> float:
+    """|least-squares slope of E/N| per 1,000 steps over the logged timed steps."""
+    import numpy as np
+    e = np.asarray(E, dtype=np.float64) / n
+    k = LOG_EVERY * np.arange(len(e), dtype=np.float64)
+    return float(abs(np.polyfit(k, e, 1)[0]) * 1000.0)
+
+
 def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int,
                path: int = 1, potential: int = 0, global_rc=None, dt: float = 0.005, T0=None):
     from paper_1105_5613_amd import System, make_params
@@ -92,7 +103,7 @@ def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_ever
     sysm.profile(prof_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sysm.step(steps, T0=T0)
+    lg = sysm.step(steps, T0=T0, log_every=LOG_EVERY)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = sysm.profile_read()
@@ -104,6 +115,7 @@ def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_ever
             "force_ms_avg": prof["force_ms"] / max(prof["force_launches"], 1),
             "force_launches_timed": prof["force_launches"], "nbar": nbar, "nmax": nmax,
             "rebuilds": obs["n_rebuild"], "steps_total": obs["step"],
+            "drift": None if T0 is not None else energy_drift(lg["E"][:, 0], n),
             "tuned": {"tpp": tuned["tpp"], "unroll": tuned["unroll"]}}
 
 
@@ -286,7 +298,7 @@ def main():
                             args.profile_every)
         log(f"  {f}: {res[f]['rate']:.4e} particle-steps/s, {res[f]['ms_per_step']:.4f} ms/step, "
             f"force {res[f]['force_ms_avg']:.4f} ms, nbar {res[f]['nbar']:.2f}, "
-            f"rebuilds {res[f]['rebuilds']}")
+            f"rebuilds {res[f]['rebuilds']}, drift {res[f]['drift']:.2e}")
     forms_out = {}
     for f, r in res.items():
         b = force_bytes_per_particle(r["nbar"], f == "mixed")
@@ -298,6 +310,7 @@ def main():
                                                 / HBM_PEAK_GBS, 4),
                         "force_traffic_bytes": None if tr is None else round(tr),
                         "mean_list_length": round(r["nbar"], 3), "rebuilds": r["rebuilds"],
+                        "energy_drift_per_particle_per_1000_steps": r["drift"],
                         "tuned": r["tuned"]}
     if "fp64" in res and "mixed" in res:
         forms_out["speedup_mixed_vs_fp64"] = round(res["mixed"]["rate"] / res["fp64"]["rate"], 4)
@@ -319,6 +332,7 @@ def main():
             "force_ms_avg": round(rl["force_ms_avg"], 4), "force_achieved_gbs": round(ach, 1),
             "force_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
             "mean_list_length": round(rl["nbar"], 3), "rebuilds": rl["rebuilds"],
+            "energy_drift_per_particle_per_1000_steps": rl["drift"],
             "tuned": rl["tuned"]}
     if "cells" in forms:
         log(f"timing the list-free cell path (FP64): {args.steps} steps")
@@ -329,7 +343,8 @@ def main():
             "workload": f"lj{n} as the headline, list-free cell path (no neighbour list; the "
                         "27-cell stencil searched in every force launch)",
             "value": round(rcell["rate"], 1), "ms_per_step": round(rcell["ms_per_step"], 5),
-            "force_ms_avg": round(rcell["force_ms_avg"], 5), "rebuilds": rcell["rebuilds"]}
+            "force_ms_avg": round(rcell["force_ms_avg"], 5), "rebuilds": rcell["rebuilds"],
+            "energy_drift_per_particle_per_1000_steps": rcell["drift"]}
         if "fp64" in res:
             forms_out["cells_fp64"]["rate_vs_list_fp64"] = round(rcell["rate"] / res["fp64"]["rate"], 4)
     if "soft" in forms:

@@ -122,12 +122,13 @@ constexpr double kFar = 1.0e300;  // x of the idle lanes of a chunk: r^2 overflo
 // Append the hits of the lane's candidate for home particle hl of the group
 // (wave-uniform) at that particle's running count cnt.  Rows below rows_lds
 // go to the wave's LDS buffer ([row][home] layout) and reach the list later
-// as whole row segments; rows above it (crowded cells only) are stored
-// straight into the list.
+// as whole row segments; rows above it are stored straight into the home
+// particle's list row hrow (a wave-uniform pointer: one scalar base plus a
+// 32-bit lane offset per store).
 template <typename E>
-__device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_t hl, int32_t ih,
+__device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_t hl,
                                     uint32_t entry, int32_t cap, int32_t rows_lds, int32_t gn,
-                                    int32_t stride, uint32_t* buf, E* __restrict__ nbr) {
+                                    uint32_t* buf, E* __restrict__ hrow) {
   if (mask) {
     const int32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
@@ -136,11 +137,29 @@ __device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_
       if (k < rows_lds)
         buf[k * gn + hl] = entry;
       else
-        nbr[list_base(ih, cap) + (size_t)k * kSlice] = (E)entry;
+        *reinterpret_cast<E*>(reinterpret_cast<char*>(hrow) +
+                              (uint32_t)k * (uint32_t)(kSlice * sizeof(E))) = (E)entry;
     }
     cnt += (int32_t)__popcll(mask);
   }
   return cnt;
+}
+
+// v[l] = x for the wave-uniform lane l (one v_writelane; the clang in use
+// has no builtin for it).  Lanes other than l keep their value.
+__device__ inline int32_t write_lane(int32_t v, int32_t x, int32_t l) {
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "s"(l));
+  return v;
+}
+
+// List row of home particle gbase + h, from the row of gbase: a group of at
+// most 64 consecutive particles spans at most two slices.
+template <typename E>
+__device__ inline E* home_row(E* grow, int32_t gbase, int32_t h, int32_t cap) {
+  const uint32_t off = (uint32_t)h + (((gbase & (kSlice - 1)) + h) >= kSlice
+                                          ? (uint32_t)(cap - 1) * (uint32_t)kSlice
+                                          : 0u);
+  return grow + __builtin_amdgcn_readfirstlane(off);
 }
 
 // Cut-off threshold of the pair (home species a, lane's candidate species b),
@@ -269,8 +288,9 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
 
   for (int32_t g0 = 0; g0 < nh; g0 += kCwGroup) {
     const int32_t gn = nh - g0 < kCwGroup ? nh - g0 : kCwGroup;
-    const int32_t gbase = h0 + g0;
+    const int32_t gbase = __builtin_amdgcn_readfirstlane(h0 + g0);  // wave-uniform
     const int32_t rows_lds = BUF / gn;
+    E* const grow = nbr + list_base(gbase, cap);
     int32_t cntv = 0;  // lane h: neighbours found so far for home gbase + h
     for (int32_t base = 0; base < ncand; base += 64) {
       const int32_t v = base + lane;
@@ -330,8 +350,9 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
             const bool hit = SELF ? (k != i0 + u && ra[u] < tha[u]) : ra[u] < tha[u];
             const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
             int32_t cu = __builtin_amdgcn_readlane(cntv, h + u);
-            cu = cw_append(m, hit, cu, h + u, i0 + u, entry, cap, rows_lds, gn, stride, buf, nbr);
-            cntv = lane == h + u ? cu : cntv;
+            cu = cw_append(m, hit, cu, h + u, entry, cap, rows_lds, gn, buf,
+                           home_row(grow, gbase, h + u, cap));
+            cntv = write_lane(cntv, cu, h + u);
           }
         }
       };
@@ -348,8 +369,8 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
         const bool hita = k != ia && ra < tha;
         const uint64_t ma = __builtin_amdgcn_ballot_w64(hita);
         int32_t ca = __builtin_amdgcn_readlane(cntv, h);
-        ca = cw_append(ma, hita, ca, h, ia, entry, cap, rows_lds, gn, stride, buf, nbr);
-        cntv = lane == h ? ca : cntv;
+        ca = cw_append(ma, hita, ca, h, entry, cap, rows_lds, gn, buf, home_row(grow, gbase, h, cap));
+        cntv = write_lane(cntv, ca, h);
       }
     }
     if (lane < gn) {

@@ -407,6 +407,25 @@ def test_graph_replays_match_direct(torch_cuda, precision):
             assert np.array_equal(a[k], b[k]), k
 
 
+def test_profiling_with_graph_steps(torch_cuda):
+    """With force-kernel timing on, a graph-configured context launches the
+    steps directly (bit-identical to its graph replays) and the timed
+    launches can be read back."""
+    say("case profiling with graph_steps")
+    ref, _ = make_system(torch_cuda, 4000, 5, graph_steps=10)
+    ref.step(20)
+    xr, vr, _ = ref.get_state()
+    sysm, _ = make_system(torch_cuda, 4000, 5, graph_steps=10)
+    sysm.profile(2)
+    sysm.step(20)
+    pr = sysm.profile_read()
+    assert pr["force_launches"] == 10
+    assert pr["force_ms"] > 0.0
+    x, v, _ = sysm.get_state()
+    assert np.array_equal(x.cpu().numpy(), xr.cpu().numpy())
+    assert np.array_equal(v.cpu().numpy(), vr.cpu().numpy())
+
+
 def test_checkpoint_resume(torch_cuda):
     """200 steps straight vs 100 + get_state/set_state + 100."""
     say("case checkpoint")
