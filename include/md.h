@@ -30,8 +30,10 @@
  *     Calls that return data to the host synchronise that stream and report
  *     device-side errors latched since the last such call.
  *   - A context is not thread-safe; distinct contexts are independent.
- *   - The library allocates its own device buffers with hipMalloc in
- *     md_init / md_build_cells and frees them in md_destroy.
+ *   - The context owns its device buffers (sorted state, cells, lists,
+ *     partials).  md_init takes them from hipMalloc; md_init_alloc from a
+ *     caller-supplied allocator (e.g. a framework's caching allocator).
+ *     They are released in md_destroy.
  */
 #ifndef MD_H
 #define MD_H
@@ -123,6 +125,27 @@ typedef struct {
  * index and a 6-bit periodic-image code). */
 md_status md_init(md_ctx* out, const md_params* p, int32_t nrep,
                   const int64_t* n, const double* L, void* hip_stream);
+
+/* Caller-supplied device allocator.  alloc(u, bytes, stream) returns at
+ * least `bytes` bytes of device memory, aligned to 256 bytes, usable in
+ * stream order on `stream` (the context's stream), or NULL on failure (the
+ * call then fails with MD_ENOMEM).  free(u, ptr, stream) takes back a
+ * pointer alloc returned; the library has synchronised the stream before
+ * calling it, so no queued work still uses ptr.  u is passed through.  The
+ * callbacks run on the thread that calls the library: in md_init_alloc,
+ * when a call grows a buffer (neighbour capacity, logs, analysis scratch)
+ * and in md_destroy. */
+typedef struct {
+  void* (*alloc)(void* u, size_t bytes, void* stream);
+  void (*free)(void* u, void* ptr, void* stream);
+  void* u;
+} md_allocator;
+
+/* md_init with every device buffer of the context taken from *alloc
+ * (alloc = NULL: hipMalloc, as md_init).  *alloc is copied; u must stay
+ * valid until md_destroy. */
+md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* n,
+                        const double* L, void* hip_stream, const md_allocator* alloc);
 
 /* Release every device buffer; ctx becomes invalid.  NULL is a no-op. */
 md_status md_destroy(md_ctx ctx);

@@ -62,6 +62,7 @@ struct md_ctx_s {
   md_obs* log_dev = nullptr;
   int64_t log_cap = 0;
   std::vector<void*> owned;
+  md_allocator alloc{};  // alloc.alloc == nullptr: hipMalloc / hipFree
   // captured K-step graphs (md_params.graph_steps)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -98,7 +99,10 @@ template <typename T>
 md_status dalloc(md_ctx c, T** ptr, size_t count) {
   void* p = nullptr;
   size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  if (c->alloc.alloc) {
+    p = c->alloc.alloc(c->alloc.u, bytes, (void*)c->stream);
+    if (!p) return fail(c, MD_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, MD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
@@ -111,7 +115,12 @@ void dfree(md_ctx c, void* p) {
   if (!p) return;
   auto it = std::find(c->owned.begin(), c->owned.end(), p);
   if (it != c->owned.end()) c->owned.erase(it);
-  (void)hipFree(p);
+  if (c->alloc.alloc) {
+    (void)hipStreamSynchronize(c->stream);  // nothing queued may still use p
+    c->alloc.free(c->alloc.u, p, (void*)c->stream);
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 double max_rc(const md_params& p) {
@@ -388,7 +397,14 @@ const char* md_last_error(md_ctx c) { return c ? c->err.c_str() : g_init_error.c
 
 md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* n,
                   const double* L, void* hip_stream) {
+  return md_init_alloc(out, p, nrep, n, L, hip_stream, nullptr);
+}
+
+md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* n,
+                        const double* L, void* hip_stream, const md_allocator* alloc) {
   if (!out) return fail(nullptr, MD_EINVAL, "out is NULL");
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(nullptr, MD_EINVAL, "allocator needs both alloc and free");
   *out = nullptr;
   std::string why;
   if (validate(p, &why)) return fail(nullptr, MD_EINVAL, why);
@@ -413,6 +429,7 @@ md_status md_init(md_ctx* out, const md_params* p, int32_t nrep, const int64_t* 
   c->tpp = p->tpp == 0 ? 2 : p->tpp;
   c->unroll = p->unroll == 0 ? 4 : p->unroll;
   c->stream = (hipStream_t)hip_stream;
+  if (alloc) c->alloc = *alloc;
 
   // replica geometry: cells of side >= max rc + skin (nc < 3 -> one cell)
   const double side = rcmax + p->skin;
@@ -679,7 +696,12 @@ md_status md_destroy(md_ctx c) {
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  for (void* p : c->owned) (void)hipFree(p);
+  for (void* p : c->owned) {
+    if (c->alloc.alloc)
+      c->alloc.free(c->alloc.u, p, (void*)c->stream);
+    else
+      (void)hipFree(p);
+  }
   c->owned.clear();
   delete c;
   return MD_OK;

@@ -148,7 +148,7 @@ __device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_
 // v[l] = x for the wave-uniform lane l (one v_writelane; the clang in use
 // has no builtin for it).  Lanes other than l keep their value.
 __device__ inline int32_t write_lane(int32_t v, int32_t x, int32_t l) {
-  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "s"(l));
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "{m0}"(l));
   return v;
 }
 

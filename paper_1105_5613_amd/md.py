@@ -23,7 +23,7 @@ MD_POT_LJ, MD_POT_SOFT = 0, 1
 MD_TRUNC_SHIFTED_FORCE, MD_TRUNC_SHIFT = 0, 1
 MD_PATH_AUTO, MD_PATH_GATHER, MD_PATH_STAGED, MD_PATH_CELLS = 0, 1, 2, 3
 
-EXPORTS = ["md_init", "md_destroy", "md_last_error", "md_set_state", "md_get_state",
+EXPORTS = ["md_init", "md_init_alloc", "md_destroy", "md_last_error", "md_set_state", "md_get_state",
            "md_build_cells", "md_forces", "md_get_forces", "md_step", "md_observables",
            "md_get_cells", "md_get_neighbors", "md_replica_info", "md_profile",
            "md_profile_read", "md_list_stats", "md_autotune", "md_msd_reference", "md_msd",
@@ -78,6 +78,8 @@ def lib():
         vp, dp, ip, lp = C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)
         L.md_init.argtypes = [C.POINTER(C.c_void_p), C.POINTER(Params), C.c_int32,
                               lp, C.POINTER(C.c_double), vp]
+        L.md_init_alloc.argtypes = [C.POINTER(C.c_void_p), C.POINTER(Params), C.c_int32,
+                                    lp, C.POINTER(C.c_double), vp, C.POINTER(Allocator)]
         L.md_destroy.argtypes = [vp]
         L.md_last_error.argtypes = [vp]
         L.md_last_error.restype = C.c_char_p
@@ -140,10 +142,46 @@ def _obs_dict(o: Obs):
     return {k: getattr(o, k) for k in OBS_KEYS}
 
 
-class System:
-    """One md context: nrep replicas (sizes ``n``, box sides ``L``)."""
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
-    def __init__(self, params: Params, n, L, stream=None):
+
+class Allocator(C.Structure):
+    """md_allocator: alloc(u, bytes, stream), free(u, ptr, stream), u."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("u", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device buffers of a context from torch's caching allocator: each block
+    is a uint8 CUDA tensor allocated on the current stream (the context's)
+    and kept alive until the library frees it."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.blocks = {}
+
+        def _alloc(u, nbytes, stream):
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device="cuda")
+            self.blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(u, ptr, stream):
+            self.blocks.pop(ptr, None)
+
+        self._fns = (ALLOC_FN(_alloc), FREE_FN(_free))  # keep the thunks alive
+        self.struct = Allocator(self._fns[0], self._fns[1], None)
+
+    def bytes_held(self):
+        return sum(t.numel() for t in self.blocks.values())
+
+
+class System:
+    """One md context: nrep replicas (sizes ``n``, box sides ``L``).  With
+    ``allocator="torch"`` the context's device buffers come from torch's
+    caching allocator (md_init_alloc), otherwise from hipMalloc."""
+
+    def __init__(self, params: Params, n, L, stream=None, allocator=None):
         import torch
         self._torch = torch
         n = [int(v) for v in (n if hasattr(n, "__len__") else [n])]
@@ -159,8 +197,16 @@ class System:
         h = C.c_void_p()
         na = (C.c_int64 * self.nrep)(*n)
         La = (C.c_double * self.nrep)(*L)
-        rc = lib().md_init(C.byref(h), C.byref(params), self.nrep, na, La,
-                           C.c_void_p(st.cuda_stream))
+        self.allocator = None
+        if allocator == "torch":
+            self.allocator = TorchAllocator()
+            rc = lib().md_init_alloc(C.byref(h), C.byref(params), self.nrep, na, La,
+                                     C.c_void_p(st.cuda_stream), C.byref(self.allocator.struct))
+        elif allocator is None:
+            rc = lib().md_init(C.byref(h), C.byref(params), self.nrep, na, La,
+                               C.c_void_p(st.cuda_stream))
+        else:
+            raise ValueError("allocator must be None or 'torch'")
         if rc != MD_OK:
             raise MDError(rc, lib().md_last_error(None).decode())
         self._h = h
