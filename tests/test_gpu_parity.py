@@ -426,6 +426,32 @@ def test_profiling_with_graph_steps(torch_cuda):
     assert np.array_equal(v.cpu().numpy(), vr.cpu().numpy())
 
 
+def test_torch_allocator(torch_cuda):
+    """Context buffers from torch's caching allocator (md_init_alloc), including
+    a neighbour-capacity growth that frees and allocates through it: the same
+    bits as hipMalloc buffers, and every block is handed back at close."""
+    from paper_1105_5613_amd import System
+    say("case torch allocator")
+    s = initconf.fcc_system(4000, seed=5, temperature=2.0)
+    outs = []
+    for alloc in (None, "torch"):
+        sysm = System(lib_params(max_neighbors=24), [4000], [s["L"]], allocator=alloc)
+        sysm.set_state(s["x"], s["v"], s["type"])
+        sysm.build_cells()  # 24 slots overflow: the capacity grows once
+        assert sysm.replica_info(0)["max_neighbors"] > 24
+        sysm.step(50)
+        x, v, _ = sysm.get_state()
+        outs.append((x.cpu().numpy(), v.cpu().numpy()))
+        a = sysm.allocator
+        if alloc:
+            assert a.bytes_held() > 0
+        sysm.close()
+        if alloc:
+            assert a.bytes_held() == 0
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_checkpoint_resume(torch_cuda):
     """200 steps straight vs 100 + get_state/set_state + 100."""
     say("case checkpoint")
