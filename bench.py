@@ -175,22 +175,30 @@ def run_one_at_a_time(torch, systems, temps, steps: int):
     return {"rate": sum(s["n"] for s in systems) * steps / wall, "steps": steps}
 
 
-def cpu_baseline(inputs, nsteps: int):
+def cpu_baseline(inputs, nsteps: int, nsteps_1t: int = 4):
     import oracle
     eps, sig, rc, mass = mixture()
     p = oracle.make_params(eps, sig, rc, mass, skin=0.3)
     sim = oracle.Sim(p, inputs["n"], inputs["L"], 0.005)
     sim.set_state(inputs["x"], inputs["v"], inputs["type"])
     sim.forces()  # first list build and F(0), untimed
+    cores = oracle.max_threads()
     t0 = time.perf_counter()
     sim.step(nsteps)
     wall = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    # the same oracle on one thread, over a shorter stretch of the same run
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    sim.step(nsteps_1t)
+    wall1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
     return {"value": inputs["n"] * nsteps / wall, "unit": "particle-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{nsteps} velocity-Verlet steps (with their list rebuilds) of the same "
                       f"{inputs['n']}-particle system after its first list build; FP64 C "
-                      f"oracle, OpenMP over particles, {wall:.1f} s"}
+                      f"oracle, OpenMP over particles, {wall:.1f} s",
+            "one_thread": {"value": inputs["n"] * nsteps_1t / wall1,
+                           "sample": f"the next {nsteps_1t} steps on one thread, {wall1:.1f} s"}}
 
 
 def calibrate_copy(torch):

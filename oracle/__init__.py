@@ -109,8 +109,19 @@ def lib():
                                      C.c_double, C.c_int64, C.POINTER(Obs)]
         L.mdref_sim_rebuilds.restype = C.c_int64
         L.mdref_sim_rebuilds.argtypes = [C.c_void_p]
+        L.mdref_set_threads.argtypes = [C.c_int32]
+        L.mdref_max_threads.restype = C.c_int32
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops (timing only)."""
+    lib().mdref_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().mdref_max_threads())
 
 
 def _f64(a, shape=None):

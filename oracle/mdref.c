@@ -9,6 +9,7 @@
 #include "mdref.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -526,6 +527,9 @@ static double kinetic(const mdref_sim* s) {
 }
 
 int64_t mdref_sim_rebuilds(const mdref_sim* s) { return s->rebuilds; }
+
+void mdref_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }
+int32_t mdref_max_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 int mdref_sim_step(mdref_sim* s, int32_t nsteps, int32_t thermostat,
                    double T0, double T1, int64_t ramp, mdref_obs* obs) {

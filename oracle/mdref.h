@@ -120,6 +120,11 @@ int mdref_sim_step(mdref_sim* s, int32_t nsteps, int32_t thermostat,
                    double T0, double T1, int64_t ramp, mdref_obs* obs);
 int64_t mdref_sim_rebuilds(const mdref_sim* s);
 
+/* OpenMP threads of the parallel loops (timing only; results do not depend
+ * on it: every parallel loop writes disjoint rows). */
+void mdref_set_threads(int32_t n);
+int32_t mdref_max_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,45 @@ def floored_err(Fa, Fb):
     return float(np.max(d / np.maximum(nb, frms)))
 
 
+def force_error_report(Fa, Fb, cond=None):
+    """The other error norms reported beside the floored e: the raw per-particle
+    ratio |dF_i| / |F_i| (p50, p99.9, max), the global |dF| / |F| and, given
+    cond_i = sum_j |F_ij|, the condition-normalised max_i |dF_i| / cond_i."""
+    d = np.linalg.norm(np.asarray(Fa, dtype=np.float64) - Fb, axis=1)
+    nb = np.linalg.norm(Fb, axis=1)
+    raw = d / np.maximum(nb, np.finfo(np.float64).tiny)
+    out = {"raw_p50": float(np.percentile(raw, 50)), "raw_p999": float(np.percentile(raw, 99.9)),
+           "raw_max": float(raw.max()),
+           "global": float(np.linalg.norm(d) / np.linalg.norm(nb))}
+    if cond is not None:
+        out["cond_max"] = float(np.max(d / cond))
+    return out
+
+
+def pair_force_sums(eps, sig, rc, types, xw, L, count, ids):
+    """cond_i = sum over the list of |f(r_ij)| for pairs within r_c (shifted-force LJ,
+    Eq. (3)), for the condition-normalised error (a report, not a pin)."""
+    eps, sig, rc = (np.asarray(a, dtype=np.float64) for a in (eps, sig, rc))
+    n, cap = ids.shape
+    i = np.repeat(np.arange(n), cap)
+    j = ids.reshape(-1)
+    m = (np.arange(cap)[None, :] < count[:, None]).reshape(-1)
+    i, j = i[m], j[m]
+    d = xw[i] - xw[j]
+    d -= L * np.rint(d / L)
+    r = np.linalg.norm(d, axis=1)
+    a, b = types[i], types[j]
+    e, s, c = eps[a, b], sig[a, b], rc[a, b]
+
+    def dv(x):
+        sr6 = (s / x) ** 6
+        return -(24.0 * e / x) * (2.0 * sr6 * sr6 - sr6)
+    f = np.where(r < c, np.abs(-dv(r) + dv(c)), 0.0)
+    out = np.zeros(n)
+    np.add.at(out, i, f)
+    return out
+
+
 def canonical(count, ids):
     """Rows of ids sorted ascending, padding with a large value past count."""
     n, cap = ids.shape

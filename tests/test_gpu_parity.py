@@ -12,8 +12,8 @@ import pytest
 
 import initconf
 import oracle
-from gpu_common import (canonical, drift_slope, floored_err, lib_params, oracle_cells_lists,
-                        oracle_params)
+from gpu_common import (canonical, drift_slope, floored_err, force_error_report, lib_params,
+                        oracle_cells_lists, oracle_params, pair_force_sums, tables)
 
 pytestmark = pytest.mark.gpu
 
@@ -139,7 +139,14 @@ def test_forces_mixed(torch_cuda, path):
     Fo, pe_i, w_i = oracle.forces_cells(p, s["x"], s["type"], s["L"])
     e = floored_err(F, Fo)
     say(f"  mixed force error {e:.3e}")
+    xw, _, _, count, ids, _ = oracle_cells_lists(p, s["x"], s["type"], s["L"])
+    eps, sig, rc, _ = tables()
+    cond = pair_force_sums(eps, sig, rc, s["type"], xw, s["L"], count, ids)
+    rep = force_error_report(F, Fo, cond)
+    say("  raw |dF|/|F|: p50 {raw_p50:.2e} p99.9 {raw_p999:.2e} max {raw_max:.2e}; "
+        "global {global:.2e}; condition-normalised max {cond_max:.2e}".format(**rep))
     assert e <= 1e-5
+    assert rep["global"] <= 1e-5 and rep["cond_max"] <= 1e-5
     ob = sysm.observables()[0]
     assert ob["pe"] == pytest.approx(pe_i.sum(), rel=1e-6)
     assert ob["virial"] == pytest.approx(w_i.sum(), rel=1e-6)
@@ -201,8 +208,11 @@ def test_nve_drift_fp64_and_mixed(torch_cuda, path):
         say(f"case drift precision={precision} {path}")
         sysm, s = make_system(torch_cuda, 4000, 1, precision=precision, **PATHS[path])
         log = sysm.step(1100, log_every=1)
-        D = drift_slope(log["E"][:, 0], 4000)
-        say(f"  drift D = {D:.3e}, rebuilds = {log['n_rebuild'][-1, 0]}")
+        E = log["E"][:, 0]
+        D = drift_slope(E, 4000)
+        tail = (E[100:] - E[100]) / 4000
+        say(f"  drift D = {D:.3e}, max |E - E(100)|/N = {np.abs(tail).max():.3e}, "
+            f"std(E/N) = {np.std(E[100:] / 4000):.3e}, rebuilds = {log['n_rebuild'][-1, 0]}")
         assert D <= 1e-4
         assert log["n_rebuild"][-1, 0] > 10
 

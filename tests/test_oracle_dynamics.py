@@ -131,3 +131,25 @@ def test_observable_definitions(oracle_lib):
     assert out["E"][-1] == pytest.approx(ke + pe, rel=1e-14)
     V = sim.L ** 3
     assert out["P"][-1] == pytest.approx((2 * ke + w) / (3 * V), rel=1e-14)
+
+
+def test_thread_count_does_not_change_results(oracle_lib):
+    """Every parallel loop of the oracle writes disjoint rows: one thread and
+    all threads give the same bits (forces, a short run with rebuilds)."""
+    o = oracle_lib
+    eps, sig, rc, mass = initconf.mixture_tables()
+    p = o.make_params(eps, sig, rc, mass, skin=0.3)
+    outs = []
+    nmax = o.max_threads()
+    try:
+        for nt in (1, max(nmax, 2)):
+            o.set_threads(nt)
+            sim, s = make(o, 4000, 3, T=2.0)
+            F, pe, w = o.forces_cells(p, s["x"], s["type"], s["L"])
+            sim.step(20)
+            x, v, img = sim.get_state()
+            outs.append((F, pe, w, x, v, img))
+    finally:
+        o.set_threads(nmax)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
