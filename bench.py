@@ -80,12 +80,18 @@ def mixture():
 LOG_EVERY = 10  # observables logged every 10 timed steps (energy drift)
 
 
-def energy_drift(E, n: int) -> float:
-    """|least-squares slope of E/N| per 1,000 steps over the logged timed steps."""
+def energy_drift(E, n: int, warmup: int):
+    """|least-squares slope of E/N| per 1,000 steps over the logged timed steps
+    from step 100 of the run on (100-step burn-in); None when fewer than 900
+    steps follow the burn-in (a short window measures the start-up transient,
+    not the drift)."""
     import numpy as np
     e = np.asarray(E, dtype=np.float64) / n
-    k = LOG_EVERY * np.arange(len(e), dtype=np.float64)
-    return float(abs(np.polyfit(k, e, 1)[0]) * 1000.0)
+    step = warmup + LOG_EVERY * (1 + np.arange(len(e), dtype=np.float64))
+    if step[-1] - 100 < 900:
+        return None
+    keep = step >= 100
+    return float(abs(np.polyfit(step[keep], e[keep], 1)[0]) * 1000.0)
 
 
 def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int,
@@ -115,7 +121,7 @@ def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_ever
             "force_ms_avg": prof["force_ms"] / max(prof["force_launches"], 1),
             "force_launches_timed": prof["force_launches"], "nbar": nbar, "nmax": nmax,
             "rebuilds": obs["n_rebuild"], "steps_total": obs["step"],
-            "drift": None if T0 is not None else energy_drift(lg["E"][:, 0], n),
+            "drift": None if T0 is not None else energy_drift(lg["E"][:, 0], n, warmup),
             "tuned": {"tpp": tuned["tpp"], "unroll": tuned["unroll"]}}
 
 
@@ -306,7 +312,7 @@ def main():
                             args.profile_every)
         log(f"  {f}: {res[f]['rate']:.4e} particle-steps/s, {res[f]['ms_per_step']:.4f} ms/step, "
             f"force {res[f]['force_ms_avg']:.4f} ms, nbar {res[f]['nbar']:.2f}, "
-            f"rebuilds {res[f]['rebuilds']}, drift {res[f]['drift']:.2e}")
+            f"rebuilds {res[f]['rebuilds']}, drift {res[f]['drift']}")
     forms_out = {}
     for f, r in res.items():
         b = force_bytes_per_particle(r["nbar"], f == "mixed")

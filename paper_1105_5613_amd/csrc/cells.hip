@@ -250,25 +250,44 @@ __global__ __launch_bounds__(1024) void k_scan_top(int32_t* __restrict__ bsum, i
 
 // Small grids: the whole exclusive scan in one block, chunk by chunk with a
 // running carry (one launch instead of three).
+// Eight consecutive counts of one thread (zeros past n), as two 16-byte
+// loads when the group lies inside the array.
+__device__ inline void load8(const int32_t* __restrict__ in, int32_t base, int32_t n,
+                             int32_t v[8]) {
+  if (base + 8 <= n) {
+    const int4 a = *reinterpret_cast<const int4*>(in + base);
+    const int4 b = *reinterpret_cast<const int4*>(in + base + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = base + e < n ? in[base + e] : 0;
+  }
+}
+
+// Exclusive scan of up to 65,536 counts in one block: 8,192 per pass, each
+// thread 8 consecutive values; the next pass's values are loaded before the
+// current pass's block scan so the passes do not each wait a full memory
+// round trip.  Requires `in` 16-byte aligned (device allocations are).
 __global__ __launch_bounds__(1024) void k_scan_single(const int32_t* __restrict__ in,
                                                       int32_t* __restrict__ out, int32_t n,
                                                       const DevState* st) {
   if (!st->any_rebuild) return;
   __shared__ int32_t wsum[16];
-  __shared__ int32_t carry_s;
-  constexpr int kPer = 8;
+  constexpr int kPer = 8, kPass = 1024 * kPer;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry_s = 0;
-  __syncthreads();
-  for (int32_t c0 = 0; c0 < n; c0 += 1024 * kPer) {
+  int32_t carry = 0;
+  int32_t cur[kPer], nxt[kPer] = {};
+  load8(in, threadIdx.x * kPer, n, cur);
+  for (int32_t c0 = 0; c0 < n; c0 += kPass) {
     const int32_t base = c0 + threadIdx.x * kPer;
+    if (c0 + kPass < n) load8(in, base + kPass, n, nxt);
     int32_t loc[kPer];
     int32_t s = 0;
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      const int32_t v = base + e < n ? in[base + e] : 0;
       loc[e] = s;
-      s += v;
+      s += cur[e];
     }
     int32_t x = s;
     for (int d = 1; d < 64; d <<= 1) {
@@ -277,20 +296,28 @@ __global__ __launch_bounds__(1024) void k_scan_single(const int32_t* __restrict_
     }
     if (lane == 63) wsum[w] = x;
     __syncthreads();
-    int32_t pre = carry_s, tot = 0;
+    int32_t pre = carry, tot = 0;
     for (int q = 0; q < 16; ++q) {
       if (q < w) pre += wsum[q];
       tot += wsum[q];
     }
     pre += x - s;
+    if (base + kPer <= n) {
+      *reinterpret_cast<int4*>(out + base) =
+          make_int4(pre + loc[0], pre + loc[1], pre + loc[2], pre + loc[3]);
+      *reinterpret_cast<int4*>(out + base + 4) =
+          make_int4(pre + loc[4], pre + loc[5], pre + loc[6], pre + loc[7]);
+    } else {
 #pragma unroll
-    for (int e = 0; e < kPer; ++e)
-      if (base + e < n) out[base + e] = pre + loc[e];
-    __syncthreads();
-    if (threadIdx.x == 0) carry_s += tot;
-    __syncthreads();
+      for (int e = 0; e < kPer; ++e)
+        if (base + e < n) out[base + e] = pre + loc[e];
+    }
+    carry += tot;
+    __syncthreads();  // wsum is rewritten by the next pass
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) cur[e] = nxt[e];
   }
-  if (threadIdx.x == 0) out[n] = carry_s;
+  if (threadIdx.x == 0) out[n] = carry;
 }
 
 __global__ void k_scan_add(int32_t* __restrict__ out, const int32_t* __restrict__ bsum,
