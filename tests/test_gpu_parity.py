@@ -84,6 +84,59 @@ def test_cells_lists_forces_fp64(torch_cuda, n, seed, kw):
     assert ob["n_rebuild"] == 1
 
 
+def boundary_state(seed):
+    """4,000-particle FCC state whose lattice planes coincide with the cell
+    faces (cell side = 2 lattice constants): every coordinate within 0.05 of a
+    face is snapped exactly onto it, and a few are set to the wrap cases of the
+    one-wrap rule: 0.0, -0.0, a tiny negative value (x + L rounds to L, which
+    the rule maps to 0), L itself, the largest double below L, and a value
+    just past L."""
+    s = initconf.fcc_system(4000, seed=seed, temperature=2.0)
+    L = s["L"]
+    x = s["x"].copy()
+    p = oracle_params()
+    nc, _ = oracle.cell_grid(p, L)
+    side = L / nc
+    k = np.rint(x / side)
+    near = np.abs(x - k * side) < 0.05
+    x[near] = (k * side)[near]
+    rng = np.random.default_rng(seed)
+    zero_plane = np.argwhere(near & (k % nc == 0))
+    pick = zero_plane[rng.choice(len(zero_plane), 6, replace=False)]
+    specials = [0.0, -0.0, -1e-17, L, np.nextafter(L, 0.0), L + 1e-14]
+    for (i, d), v in zip(pick, specials):
+        x[i, d] = v
+    return s, x, int(near.sum())
+
+
+@pytest.mark.parametrize("precision,path", [(0, 1), (0, 2), (1, 1), (0, 3)])
+def test_cell_faces_and_wrap_cases(torch_cuda, precision, path):
+    """Particles exactly on cell faces and at the wrap edge cases: wrapped
+    positions, image counters, cell arrays and lists bit-exact, forces within
+    the bar."""
+    from paper_1105_5613_amd import System
+    s, x, nsnap = boundary_state(31)
+    say(f"case cell faces precision={precision} path={path}: {nsnap} coordinates on faces")
+    sysm = System(lib_params(precision=precision, path=path), [4000], [s["L"]])
+    sysm.set_state(x, s["v"], s["type"])
+    sysm.build_cells()
+    p = oracle_params()
+    xw, img, _, cs, order, nc = oracle.build_cells(p, x, s["L"])
+    gx, _, gimg = sysm.get_state()
+    assert np.array_equal(gx.cpu().numpy(), xw), "wrapped positions differ"
+    assert np.array_equal(gimg.cpu().numpy(), img), "image counters differ"
+    gcs, gorder = sysm.get_cells(0)
+    assert np.array_equal(gcs, cs) and np.array_equal(gorder, order)
+    if path != 3:
+        compare_cells_lists(sysm, p, x, s["type"], s["L"], tag="faces")
+    sysm.forces()
+    F = sysm.get_forces().cpu().numpy()
+    Fo, _, _ = oracle.forces_cells(p, xw, s["type"], s["L"])
+    e = floored_err(F, Fo)
+    say(f"  force error {e:.3e}")
+    assert e <= (1e-12 if precision == 0 else 1e-5)
+
+
 # Species tables beyond the binary mixture.  The list test forms the pair
 # threshold either as one FMA over the home species value (one species, or two
 # whose thresholds for each partner species lie within a factor of two) or by
