@@ -7,13 +7,15 @@ energy/virial <= 1e-6 relative.  Every comparison is on the same state
 (downloaded from the GPU when the GPU has been stepping): trajectories of two
 chaotic integrations are never compared beyond a few steps.
 """
+import math
+
 import numpy as np
 import pytest
 
 import initconf
 import oracle
-from gpu_common import (canonical, drift_slope, floored_err, force_error_report, lib_params,
-                        oracle_cells_lists, oracle_params, pair_force_sums, tables)
+from gpu_common import (SKIN, canonical, drift_slope, floored_err, force_error_report,
+                        lib_params, oracle_cells_lists, oracle_params, pair_force_sums, tables)
 
 pytestmark = pytest.mark.gpu
 
@@ -135,6 +137,56 @@ def test_cell_faces_and_wrap_cases(torch_cuda, precision, path):
     e = floored_err(F, Fo)
     say(f"  force error {e:.3e}")
     assert e <= (1e-12 if precision == 0 else 1e-5)
+
+
+def threshold_pairs():
+    """Isolated pairs at the list threshold of their species pair: along x at
+    d = sqrt(thr) + k ulp (k = -3..3; the difference of the two coordinates is
+    exact, so r^2 = round(d d) lands below, on and above thr), and along random
+    directions at (1 + k 1e-16) sqrt(thr).  Pairs sit 8 sigma apart in a
+    40-sigma box, so no other particle is within the threshold."""
+    eps, sig, rc, mass = tables()
+    L = 40.0
+    xs, ts = [], []
+    slots = [(a, b, c) for a in range(5) for b in range(5) for c in range(5)]
+    rng = np.random.default_rng(12)
+    q = 0
+    for ta, tb in ((0, 0), (0, 1), (1, 1)):
+        t = (rc[ta][tb] + SKIN) * (rc[ta][tb] + SKIN)
+        d0 = math.sqrt(t)
+        for k in range(-3, 4):
+            d = d0
+            for _ in range(abs(k)):
+                d = np.nextafter(d, np.inf if k > 0 else -np.inf)
+            o = 8.0 * np.array(slots[q], dtype=np.float64) + 1.0
+            q += 1
+            xs += [o, o + np.array([d, 0.0, 0.0])]
+            ts += [ta, tb]
+        for k in range(-3, 4):
+            u = rng.standard_normal(3)
+            u /= np.linalg.norm(u)
+            o = 8.0 * np.array(slots[q], dtype=np.float64) + 1.0
+            q += 1
+            xs += [o, o + u * d0 * (1.0 + k * 1e-16)]
+            ts += [ta, tb]
+    return np.array(xs), np.array(ts, dtype=np.int32), L
+
+
+@pytest.mark.parametrize("precision,path", [(0, 1), (0, 2), (1, 1)])
+def test_list_threshold_ties(torch_cuda, precision, path):
+    """Pairs at r^2 just below, equal to and just above (r_c,ab + skin)^2: the
+    strict inclusion test gives bit-identical lists to the oracle's."""
+    from paper_1105_5613_amd import System
+    x, types, L = threshold_pairs()
+    n = len(x)
+    say(f"case threshold ties precision={precision} path={path}: {n // 2} pairs")
+    sysm = System(lib_params(precision=precision, path=path), [n], [L])
+    sysm.set_state(x, np.zeros_like(x), types)
+    sysm.build_cells()
+    p = oracle_params()
+    _, count, _ = compare_cells_lists(sysm, p, x, types, L, tag="threshold ties")
+    say(f"  pairs listed: {int(count.sum()) // 2} of {n // 2}")
+    assert 0 < count.sum() < n  # some pairs in, some out
 
 
 # Species tables beyond the binary mixture.  The list test forms the pair
