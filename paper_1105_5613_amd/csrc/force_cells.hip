@@ -37,6 +37,7 @@ struct PairLds {
 constexpr int kCellHomes = 128;  // home particles per block (one lane each)
 constexpr int kHitBuf = 16;      // buffered hits per lane before a flush
 constexpr int kCand = 8;         // candidates tested per step of the search
+constexpr double kFar = 1.0e300; // x of the idle lanes: every r^2 is +inf
 
 template <int BT>
 __device__ inline void block_sum3(double& a, double& b, double& c) {
@@ -96,7 +97,10 @@ __device__ inline void pair_force(const PairLds<T>& P, const double4& p, int32_t
   a.w += fr * r2;
 }
 
-template <bool MIXED, int MODE>
+// NT = 2: the cutoff of (home species a, candidate species value s_b) is
+// rc2[0][a] + (rc2[1][a] - rc2[0][a]) s_b as one FMA (exact: the launch checks
+// the table, see fma_pair_form; the table is symmetric); NT = 4: a select.
+template <bool MIXED, int MODE, int NT>
 __global__ __launch_bounds__(kCellHomes) void k_force_cells(
     const RowTile* __restrict__ rtiles, const RepDesc* __restrict__ reps,
     const PairTab* __restrict__ tab, const int32_t* __restrict__ cell_start,
@@ -148,6 +152,25 @@ __global__ __launch_bounds__(kCellHomes) void k_force_cells(
     int32_t cnt = 0;
     const double rc2_0 = P.rc2[ti * 4], rc2_1 = P.rc2[ti * 4 + 1], rc2_2 = P.rc2[ti * 4 + 2],
                  rc2_3 = P.rc2[ti * 4 + 3];
+    const double drc2 = P.rc2[4 + ti] - P.rc2[ti];
+    const double px = mine ? p.x : kFar;
+    // candidate c (index j, piece pc) against the lane's home particle;
+    // only the home cell's own piece can hold the particle itself
+    auto test = [&](auto self_tag, const double4& c, int32_t j, int32_t pc, double hx, double hy,
+                    double hz) {
+      constexpr bool SELF = decltype(self_tag)::value;
+      const double ex = hx - c.x, ey = hy - c.y, ez = hz - c.z;
+      const double r2 = ex * ex + ey * ey + ez * ez;
+      double rc2;
+      if constexpr (NT == 2) {
+        rc2 = __builtin_fma(drc2, c.w, rc2_0);
+      } else {
+        const int32_t tj = (int32_t)c.w;
+        rc2 = tj == 0 ? rc2_0 : (tj == 1 ? rc2_1 : (tj == 2 ? rc2_2 : rc2_3));
+      }
+      const bool hit = SELF ? (j != i && r2 < rc2) : r2 < rc2;
+      if (hit) s_hit[cnt++][threadIdx.x] = (uint32_t)j | ((uint32_t)pc << 26);
+    };
     auto flush = [&]() {
       int32_t mx = cnt;
 #pragma unroll
@@ -171,39 +194,29 @@ __global__ __launch_bounds__(kCellHomes) void k_force_cells(
           const int32_t a0 = max(u0, S.pc_l[pc]), a1 = min(u1, S.pc_l[pc + 1]);
           if (a0 >= a1) continue;
           // home position minus the piece's shift: d = x_i - (x_j + s L)
-          const double hx = p.x - S.pc_sx[pc], hy = p.y - S.pc_sy[pc], hz = p.z - S.pc_sz[pc];
+          const double hx = px - S.pc_sx[pc], hy = p.y - S.pc_sy[pc], hz = p.z - S.pc_sz[pc];
           const int32_t g = __builtin_amdgcn_readfirstlane(S.pc_g[pc] + (a0 - S.pc_l[pc]));
           const int32_t m = a1 - a0;
-          // kCand candidates per step: their scalar loads are issued together
-          int32_t t = 0;
-          for (; t + kCand <= m; t += kCand) {
-            if (__ballot(cnt > kHitBuf - kCand)) flush();
-            double4 cd[kCand];
+          auto scan = [&](auto self_tag) {
+            // kCand candidates per step: their scalar loads are issued together
+            int32_t t = 0;
+            for (; t + kCand <= m; t += kCand) {
+              if (__ballot(cnt > kHitBuf - kCand)) flush();
+              double4 cd[kCand];
 #pragma unroll
-            for (int u = 0; u < kCand; ++u) cd[u] = pos[g + t + u];  // wave-uniform
+              for (int u = 0; u < kCand; ++u) cd[u] = pos[g + t + u];  // wave-uniform
 #pragma unroll
-            for (int u = 0; u < kCand; ++u) {
-              const int32_t j = g + t + u;
-              const double ex = hx - cd[u].x, ey = hy - cd[u].y, ez = hz - cd[u].z;
-              const double r2 = ex * ex + ey * ey + ez * ez;
-              const int32_t tj = (int32_t)cd[u].w;
-              const double rc2 =
-                  tj == 0 ? rc2_0 : (tj == 1 ? rc2_1 : (tj == 2 ? rc2_2 : rc2_3));
-              if (mine && j != i && r2 < rc2)
-                s_hit[cnt++][threadIdx.x] = (uint32_t)j | ((uint32_t)pc << 26);
+              for (int u = 0; u < kCand; ++u) test(self_tag, cd[u], g + t + u, pc, hx, hy, hz);
             }
-          }
-          for (; t < m; ++t) {
-            if (__ballot(cnt == kHitBuf)) flush();
-            const int32_t j = g + t;
-            const double4 c = pos[j];
-            const double ex = hx - c.x, ey = hy - c.y, ez = hz - c.z;
-            const double r2 = ex * ex + ey * ey + ez * ez;
-            const int32_t tj = (int32_t)c.w;
-            const double rc2 = tj == 0 ? rc2_0 : (tj == 1 ? rc2_1 : (tj == 2 ? rc2_2 : rc2_3));
-            if (mine && j != i && r2 < rc2)
-              s_hit[cnt++][threadIdx.x] = (uint32_t)j | ((uint32_t)pc << 26);
-          }
+            for (; t < m; ++t) {
+              if (__ballot(cnt == kHitBuf)) flush();
+              test(self_tag, pos[g + t], g + t, pc, hx, hy, hz);
+            }
+          };
+          if (pc == 13)  // row 4 (the home row), main piece
+            scan(std::true_type{});
+          else
+            scan(std::false_type{});
         }
       }
       flush();
@@ -267,18 +280,22 @@ __global__ __launch_bounds__(kTile) void k_commit_order(
 
 int32_t cells_homes_per_block() { return kCellHomes; }
 
-void launch_force_cells(hipStream_t s, int32_t mixed, int32_t mode, int32_t nrt,
-                        const RowTile* rtiles, const RepDesc* reps, const PairTab* tab,
-                        const int32_t* cell_start, const double4* pos, double* vel, void* frc,
-                        int32_t stride, double dt, double* part, DevState* st) {
-#define KC(M, MO)                                                                            \
-  k_force_cells<M, MO><<<nrt, kCellHomes, 0, s>>>(rtiles, reps, tab, cell_start, pos, vel, \
-                                                  frc, stride, dt, part, st)
+void launch_force_cells(hipStream_t s, int32_t mixed, int32_t mode, int32_t rc2_form,
+                        int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
+                        const PairTab* tab, const int32_t* cell_start, const double4* pos,
+                        double* vel, void* frc, int32_t stride, double dt, double* part,
+                        DevState* st) {
+#define KC(M, MO, NT)                                                                 \
+  k_force_cells<M, MO, NT><<<nrt, kCellHomes, 0, s>>>(rtiles, reps, tab, cell_start, pos, \
+                                                      vel, frc, stride, dt, part, st)
+#define KN(M, MO) \
+  if (rc2_form == 2) KC(M, MO, 2); else KC(M, MO, 4)
   if (mixed) {
-    if (mode) KC(true, 1); else KC(true, 0);
+    if (mode) { KN(true, 1); } else { KN(true, 0); }
   } else {
-    if (mode) KC(false, 1); else KC(false, 0);
+    if (mode) { KN(false, 1); } else { KN(false, 0); }
   }
+#undef KN
 #undef KC
 }
 

@@ -33,7 +33,8 @@ struct md_ctx_s {
   RepDesc* reps = nullptr;
   Tile* tiles = nullptr;
   PairTab* tab = nullptr;
-  int32_t thr_form = 4;  // list threshold form of the neighbour search (list_thr_form)
+  int32_t thr_form = 4;  // form of the list thresholds in the neighbour search (fma_pair_form)
+  int32_t rc2_form = 4;  // form of the force cutoffs on the list-free path
   DevState* st = nullptr;
   int32_t *cell_rep = nullptr, *counts = nullptr, *cell_start = nullptr, *bsum = nullptr;
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp_src = nullptr;
@@ -223,8 +224,9 @@ void run_chain(md_ctx c, hipStream_t s) {
 
 void launch_forces(md_ctx c, int32_t mode, hipStream_t s) {
   if (c->cells)
-    launch_force_cells(s, c->mixed, mode, c->nrt, c->rtiles, c->reps, c->tab, c->cell_start,
-                       c->pos, c->vel, c->frc, c->stride, c->p.dt, c->part, c->st);
+    launch_force_cells(s, c->mixed, mode, c->rc2_form, c->nrt, c->rtiles, c->reps, c->tab,
+                       c->cell_start, c->pos, c->vel, c->frc, c->stride, c->p.dt, c->part,
+                       c->st);
   else if (c->staged)
     launch_force_staged(s, c->mixed, mode, c->tpp, c->unroll, c->nrt, c->rtiles, c->reps,
                         c->tab, c->cell_start, c->pos, c->vel, c->frc, c->nbr16, c->ncount,
@@ -584,7 +586,8 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
     tab.mass[a] = a < p->ntypes ? p->mass[a] : 1.0;
     tab.inv_mass[a] = 1.0 / tab.mass[a];
   }
-  c->thr_form = list_thr_form(tab, p->ntypes);
+  c->thr_form = fma_pair_form(tab.thr, p->ntypes);
+  c->rc2_form = fma_pair_form(tab.rc2, p->ntypes);
 
   std::vector<int32_t> cell_rep(c->ncells);
   for (int r = 0; r < nrep; ++r) {

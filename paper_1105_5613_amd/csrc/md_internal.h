@@ -149,10 +149,21 @@ void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* tmp_src, int32_t stride, const int32_t* id,
                         const double4* pos, const double* vel, int32_t* id_tmp,
                         double4* pos_tmp, double* vel_tmp, const DevState* st);
-// nlist.hip.  thr_form = 2: every pair threshold of the list test is formed
-// as thr[0][b] + (thr[1][b] - thr[0][b]) * species_a in one FMA, exact when
-// list_thr_form() says so; 4: a select chain over up to four species.
-int32_t list_thr_form(const PairTab& tab, int32_t ntypes);
+// Form of a symmetric species-pair table t[a * 4 + b] (a, b < ntypes) in the
+// cut-off tests: 2 when every entry is t[0][b] + (t[1][b] - t[0][b]) * s_a
+// for the species value s_a in {0.0, 1.0} as one FMA, bit for bit -- one
+// species, or two whose entries for each b lie within a factor of two (then
+// t[1][b] - t[0][b] is exact, Sterbenz); 4 otherwise (a select chain).
+inline int32_t fma_pair_form(const double* t, int32_t ntypes) {
+  if (ntypes == 1) return 2;  // s_a = 0 only: fma(d, 0, t0) = t0 for any finite d
+  if (ntypes > 2) return 4;
+  for (int b = 0; b < 2; ++b) {
+    const double t0 = t[b], t1 = t[4 + b];
+    if (!(t0 * 0.5 <= t1 && t1 <= 2.0 * t0)) return 4;
+  }
+  return 2;
+}
+// nlist.hip.  thr_form: fma_pair_form of the list thresholds.
 void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                   const int32_t* rebuild, const PairTab* tab, int32_t thr_form,
                   const int32_t* cell_start, int32_t stride, int32_t cap,
@@ -238,10 +249,12 @@ void launch_decode_staged(hipStream_t s, int32_t nrt, const RowTile* rtiles, con
                           const int32_t* ncount, uint32_t* out);
 // list-free cell path (force_cells.hip)
 int32_t cells_homes_per_block();
-void launch_force_cells(hipStream_t s, int32_t mixed, int32_t mode, int32_t nrt,
-                        const RowTile* rtiles, const RepDesc* reps, const PairTab* tab,
-                        const int32_t* cell_start, const double4* pos, double* vel, void* frc,
-                        int32_t stride, double dt, double* part, DevState* st);
+// rc2_form: fma_pair_form of the squared force cutoffs.
+void launch_force_cells(hipStream_t s, int32_t mixed, int32_t mode, int32_t rc2_form,
+                        int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
+                        const PairTab* tab, const int32_t* cell_start, const double4* pos,
+                        double* vel, void* frc, int32_t stride, double dt, double* part,
+                        DevState* st);
 void launch_commit_order(hipStream_t s, int32_t ntiles, const Tile* tiles,
                          const int32_t* rebuild, int32_t stride, const double4* pos_tmp,
                          const double* vel_tmp, const int32_t* id_tmp, double4* pos,

@@ -414,16 +414,6 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
 
 }  // namespace
 
-int32_t list_thr_form(const PairTab& tab, int32_t ntypes) {
-  if (ntypes == 1) return 2;  // species 0 only: fma(d, 0, t0) = t0 for any finite d
-  if (ntypes > 2) return 4;
-  for (int b = 0; b < 2; ++b) {
-    const double t0 = tab.thr[b], t1 = tab.thr[4 + b];
-    if (!(t0 * 0.5 <= t1 && t1 <= 2.0 * t0)) return 4;  // t1 - t0 might round
-  }
-  return 2;
-}
-
 void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                   const int32_t* rebuild, const PairTab* tab, int32_t thr_form,
                   const int32_t* cell_start, int32_t stride, int32_t cap,
