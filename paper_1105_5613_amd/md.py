@@ -153,16 +153,18 @@ class Allocator(C.Structure):
 
 class TorchAllocator:
     """Device buffers of a context from torch's caching allocator: each block
-    is a uint8 CUDA tensor allocated on the current stream (the context's)
-    and kept alive until the library frees it."""
+    is a uint8 CUDA tensor allocated on the context's stream and kept alive
+    until the library frees it (after synchronising that stream)."""
 
-    def __init__(self):
+    def __init__(self, stream):
         import torch
         self._torch = torch
+        self._stream = stream
         self.blocks = {}
 
-        def _alloc(u, nbytes, stream):
-            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device="cuda")
+        def _alloc(u, nbytes, hip_stream):
+            with self._torch.cuda.stream(self._stream):
+                t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device="cuda")
             self.blocks[t.data_ptr()] = t
             return t.data_ptr()
 
@@ -199,7 +201,7 @@ class System:
         La = (C.c_double * self.nrep)(*L)
         self.allocator = None
         if allocator == "torch":
-            self.allocator = TorchAllocator()
+            self.allocator = TorchAllocator(st)
             rc = lib().md_init_alloc(C.byref(h), C.byref(params), self.nrep, na, La,
                                      C.c_void_p(st.cuda_stream), C.byref(self.allocator.struct))
         elif allocator is None:
