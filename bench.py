@@ -54,6 +54,34 @@ def force_bytes_per_particle(nbar: float, mixed: bool) -> float:
     return 4 + 4 * nbar + 24 + 4 + (12 if mixed else 24) + 48
 
 
+def step_bytes_per_particle(nbar: float, mixed: bool, rebuilds_per_step: float) -> float:
+    """Algorithmic HBM bytes per particle-step of the whole step: the force
+    launch, the kick-drift (x, v, F, x_ref read; x, v written: 160 B FP64, 180
+    B mixed with the 16-byte record) and one rebuild (bin 28, sort keys 24,
+    reorder 160, list write 4 nbar + 4) times the measured rebuilds per step."""
+    kick = 180.0 if mixed else 160.0
+    rebuild = 28 + 24 + 160 + 4 * nbar + 4
+    return force_bytes_per_particle(nbar, mixed) + kick + rebuild * rebuilds_per_step
+
+
+def copy_gbs(torch) -> float:
+    """HBM bandwidth of a plain 1 GiB device copy (read + write), timed with
+    events over 5 copies after one warm-up copy."""
+    a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
+
+
 def src_sha() -> str:
     return hashlib.sha256(open(FORCE_SRC, "rb").read()).hexdigest()
 
@@ -323,6 +351,11 @@ def main():
                         "force_frac_hbm": round(n * b / (max(r["force_ms_avg"], 1e-12) * 1e-3) / 1e9
                                                 / HBM_PEAK_GBS, 4),
                         "force_traffic_bytes": None if tr is None else round(tr),
+                        "force_traffic_over_algorithmic": None if tr is None else round(tr / (n * b), 3),
+                        "step_algorithmic_frac_hbm": round(
+                            r["rate"] * step_bytes_per_particle(
+                                r["nbar"], f == "mixed",
+                                r["rebuilds"] / max(r["steps_total"], 1)) / 1e9 / HBM_PEAK_GBS, 4),
                         "mean_list_length": round(r["nbar"], 3), "rebuilds": r["rebuilds"],
                         "energy_drift_per_particle_per_1000_steps": r["drift"],
                         "tuned": r["tuned"]}
@@ -409,6 +442,13 @@ def main():
                 "kernel": "k_force (pair forces + fused second half kick)",
                 "algorithmic_bytes_per_launch": round(n * bpp),
                 "force_ms_avg": round(head["force_ms_avg"], 5)}
+        cgbs = copy_gbs(torch)
+        roof["copy_gbs_measured"] = round(cgbs, 1)
+        roof["frac_of_copy"] = round(achieved / cgbs, 4)
+        if traffic is not None:
+            tgbs = traffic / (head["force_ms_avg"] * 1e-3) / 1e9
+            roof["traffic_gbs"] = round(tgbs, 1)
+            roof["traffic_frac_of_copy"] = round(tgbs / cgbs, 4)
     cpu = None
     if not args.no_cpu_baseline and head is not None:
         log(f"timing the CPU oracle: {args.cpu_steps} steps")
