@@ -445,7 +445,7 @@ def main():
         cgbs = copy_gbs(torch)
         roof["copy_gbs_measured"] = round(cgbs, 1)
         roof["frac_of_copy"] = round(achieved / cgbs, 4)
-        if traffic is not None:
+        if traffic is not None and head["force_ms_avg"] > 0:
             tgbs = traffic / (head["force_ms_avg"] * 1e-3) / 1e9
             roof["traffic_gbs"] = round(tgbs, 1)
             roof["traffic_frac_of_copy"] = round(tgbs / cgbs, 4)
