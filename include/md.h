@@ -188,7 +188,12 @@ md_status md_get_forces(md_ctx ctx, void* F);
  * this call (k = 1..nsteps) rescales velocities to
  * T_target = T0 + (T1 - T0) min(k / ramp_steps, 1)  (ramp_steps <= 0: T0).
  * log: HOST [nsteps / log_every][nrep] observables of every log_every-th
- * step, or NULL.  Synchronises at the end and reports latched errors. */
+ * step, or NULL.  Synchronises at the end and reports latched errors.
+ * Forces, kinetic energy and T are formed every step; the pair sums behind
+ * pe, virial, P and E only on the logged steps and the last step of the
+ * call (inside a hipGraph chunk: also its last step, and every step when
+ * log_every does not divide graph_steps), so the observables after md_step
+ * and every log record are complete. */
 md_status md_step(md_ctx ctx, int32_t nsteps, const double* T0,
                   const double* T1, int64_t ramp_steps, md_obs* log,
                   int32_t log_every);

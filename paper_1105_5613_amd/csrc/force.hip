@@ -90,7 +90,9 @@ __device__ inline void block_sum3(double& a, double& b, double& c) {
   }
 }
 
-template <bool MIXED, int MODE, int TPP, int U>
+// EN = false (in-step launches on steps whose observables are not read):
+// the per-pair energy and virial terms are skipped and their partials are 0.
+template <bool MIXED, int MODE, int TPP, int U, bool EN>
 __global__ __launch_bounds__(kTile) void k_force(
     const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
     const PairTab* __restrict__ tab, const double4* __restrict__ pos,
@@ -173,9 +175,11 @@ __global__ __launch_bounds__(kTile) void k_force(
             fx += fr * ddx;
             fy += fr * ddy;
             fz += fr * ddz;
-            pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
-                    (r2 * rinv - P.rc[ab]) * P.fs[ab];
-            w_i += fr * r2;
+            if constexpr (EN) {
+              pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
+                      (r2 * rinv - P.rc[ab]) * P.fs[ab];
+              w_i += fr * r2;
+            }
           }
         }
 #pragma unroll
@@ -216,9 +220,11 @@ __global__ __launch_bounds__(kTile) void k_force(
             fx += fr * dx;
             fy += fr * dy;
             fz += fr * dz;
-            pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
-                    (r2 * rinv - P.rc[ab]) * P.fs[ab];
-            w_i += fr * r2;
+            if constexpr (EN) {
+              pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
+                      (r2 * rinv - P.rc[ab]) * P.fs[ab];
+              w_i += fr * r2;
+            }
           }
         }
 #pragma unroll
@@ -266,13 +272,13 @@ __global__ __launch_bounds__(kTile) void k_force(
   }
 }
 
-template <bool MIXED, int MODE>
+template <bool MIXED, int MODE, bool EN>
 void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const Tile* tiles,
               const RepDesc* reps, const PairTab* tab, const double4* pos, const float4* pos16,
               double* vel, void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
               int32_t cap, double dt, double* part, DevState* st) {
 #define KF(TPP, U)                                                                       \
-  k_force<MIXED, MODE, TPP, U><<<ntiles * TPP, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, \
+  k_force<MIXED, MODE, TPP, U, EN><<<ntiles * TPP, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, \
                                                               vel, frc, nbr, ncount, stride, \
                                                               cap, dt, part, st)
   const int key = tpp * 16 + unroll;
@@ -295,18 +301,23 @@ void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const 
 
 // Partials: one FP64 triple (pe, w, ke) per logical block; with tpp lanes
 // per particle, tile t owns logical blocks [t*tpp, (t+1)*tpp).
-void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
-                  int32_t ntiles, const Tile* tiles, const RepDesc* reps, const PairTab* tab,
-                  const double4* pos, const float4* pos16, double* vel, void* frc,
-                  const uint32_t* nbr, const int32_t* ncount, int32_t stride, int32_t cap,
-                  double dt, double* part, DevState* st) {
-#define LT(M, MO)                                                                        \
-  launch_t<M, MO>(s, tpp, unroll, ntiles, tiles, reps, tab, pos, pos16, vel, frc, nbr,    \
-                  ncount, stride, cap, dt, part, st)
+void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t energy, int32_t tpp,
+                  int32_t unroll, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
+                  const PairTab* tab, const double4* pos, const float4* pos16, double* vel,
+                  void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
+                  int32_t cap, double dt, double* part, DevState* st) {
+#define LT(M, MO, EN)                                                                    \
+  launch_t<M, MO, EN>(s, tpp, unroll, ntiles, tiles, reps, tab, pos, pos16, vel, frc, nbr, \
+                      ncount, stride, cap, dt, part, st)
+  // mode 0 (a plain force evaluation) always forms the energies
   if (mixed) {
-    if (mode) LT(true, 1); else LT(true, 0);
+    if (mode == 0) LT(true, 0, true);
+    else if (energy) LT(true, 1, true);
+    else LT(true, 1, false);
   } else {
-    if (mode) LT(false, 1); else LT(false, 0);
+    if (mode == 0) LT(false, 0, true);
+    else if (energy) LT(false, 1, true);
+    else LT(false, 1, false);
   }
 #undef LT
 }

@@ -90,7 +90,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
                                                         const double* __restrict__ part,
                                                         const double* __restrict__ dmax,
                                                         const double* __restrict__ part2,
-                                                        int32_t step, ThermoArgs ta,
+                                                        int32_t step, int32_t energy,
+                                                        ThermoArgs ta,
                                                         int64_t* __restrict__ kcall,
                                                         double* __restrict__ lam,
                                                         int32_t* __restrict__ rebuild,
@@ -126,8 +127,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
   const double pe = red[0][0], w = red[1][0];
   double ke = red[2][0];
   md_obs o = obs[r];
-  o.pe = pe;
-  o.virial = w;
+  if (energy) {
+    o.pe = pe;
+    o.virial = w;
+  }
   o.T_target = 0.0;
   if (step) o.max_disp = sqrt(red[3][0]);
   if (step) {
@@ -155,8 +158,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
   }
   o.ke = ke;
   o.T = 2.0 * ke / R.dof;
-  o.P = (2.0 * ke + w) / (3.0 * R.volume);
-  o.E = ke + pe;
+  if (energy) {
+    o.P = (2.0 * ke + w) / (3.0 * R.volume);
+    o.E = ke + pe;
+  }
   obs[r] = o;
   if (step && ta.log_every > 0) {
     const int64_t k = kcall[r];
@@ -252,10 +257,11 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
 }
 
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
-                   const double* dmax, const double* part2, int32_t step, ThermoArgs ta,
-                   int64_t* kcall, double* lam, int32_t* rebuild, md_obs* obs, DevState* st) {
-  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, dmax, part2, step, ta, kcall, lam, rebuild,
-                                        obs, st);
+                   const double* dmax, const double* part2, int32_t step, int32_t energy,
+                   ThermoArgs ta, int64_t* kcall, double* lam, int32_t* rebuild, md_obs* obs,
+                   DevState* st) {
+  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, dmax, part2, step, energy, ta, kcall, lam,
+                                        rebuild, obs, st);
 }
 
 void launch_reduce_chunks(hipStream_t s, int32_t nchunks, const RedChunk* ch, const double* part,

@@ -222,7 +222,8 @@ void run_chain(md_ctx c, hipStream_t s) {
                  c->any_multi, c->pos16);
 }
 
-void launch_forces(md_ctx c, int32_t mode, hipStream_t s) {
+// energy: form PE and W (the staged and list-free kernels always do).
+void launch_forces(md_ctx c, int32_t mode, hipStream_t s, int32_t energy = 1) {
   if (c->cells)
     launch_force_cells(s, c->mixed, mode, c->rc2_form, c->nrt, c->rtiles, c->reps, c->tab,
                        c->cell_start, c->pos, c->vel, c->frc, c->stride, c->p.dt, c->part,
@@ -232,7 +233,7 @@ void launch_forces(md_ctx c, int32_t mode, hipStream_t s) {
                         c->tab, c->cell_start, c->pos, c->vel, c->frc, c->nbr16, c->ncount,
                         c->stride, c->cap, c->lcap_f, c->p.dt, c->part, c->st);
   else
-    launch_force(s, c->mixed, mode, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps,
+    launch_force(s, c->mixed, mode, energy, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps,
                  c->tab, c->pos, c->pos16, c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap,
                  c->p.dt, c->part, c->st);
 }
@@ -283,10 +284,11 @@ ThermoArgs no_thermo() {
   return t;
 }
 
-void launch_reductions(md_ctx c, hipStream_t s, int32_t step, const ThermoArgs& ta) {
+void launch_reductions(md_ctx c, hipStream_t s, int32_t step, const ThermoArgs& ta,
+                       int32_t energy = 1) {
   if (c->nchunks) launch_reduce_chunks(s, c->nchunks, c->chunks, c->part, c->dmax, step, c->part2);
-  launch_reduce(s, c->nrep, c->reps, c->part, c->dmax, c->nchunks ? c->part2 : nullptr, step, ta,
-                c->kcall, c->lam, c->rebuild, c->obs, c->st);
+  launch_reduce(s, c->nrep, c->reps, c->part, c->dmax, c->nchunks ? c->part2 : nullptr, step,
+                energy, ta, c->kcall, c->lam, c->rebuild, c->obs, c->st);
 }
 
 // Split every replica's partial blocks [fb0, fb1) (and drift tiles) into
@@ -326,7 +328,9 @@ void launch_forces0(md_ctx c) {
 
 
 // One velocity-Verlet step on stream s (also used while capturing a graph).
-md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t thermo, int32_t k) {
+// energy: the step forms PE and W (the observables refreshed on it).
+md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t thermo, int32_t k,
+                       int32_t energy) {
   launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16,
                     c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->dmax,
                     c->st);
@@ -336,13 +340,27 @@ md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t th
     if (c->ev_pool.size() < c->ev_used + 2) return fail(c, MD_EHIP, "event pool exhausted");
     HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
   }
-  launch_forces(c, 1, s);
+  launch_forces(c, 1, s, energy);
   if (timed) {
     HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
     c->ev_used += 2;
   }
-  launch_reductions(c, s, 1, ta);
+  launch_reductions(c, s, 1, ta, energy);
   return MD_OK;
+}
+
+// Steps that form PE and W: the logged ones and the last of the run (the
+// observables md_observables returns).  Inside a K-step graph: the logged
+// steps when the log cadence divides K (the same steps in every replay),
+// every step otherwise, and always the graph's last step.
+int32_t energy_step(const ThermoArgs& ta, int64_t k, int64_t last) {
+  if (k == last) return 1;
+  return ta.log_every > 0 && (k + 1) % ta.log_every == 0;
+}
+int32_t energy_step_graph(const ThermoArgs& ta, int32_t k, int32_t K) {
+  if (k == K - 1) return 1;
+  if (ta.log_every <= 0) return 0;
+  return K % ta.log_every != 0 || (k + 1) % ta.log_every == 0;
 }
 
 md_status reserve_events(md_ctx c, int32_t nsteps) {
@@ -373,7 +391,8 @@ md_status ensure_graph(md_ctx c, const ThermoArgs& ta, int32_t thermo, int32_t K
   md_status rc = reserve_events(c, K);
   if (rc) return rc;
   HIPCHECK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-  for (int32_t k = 0; k < K && rc == MD_OK; ++k) rc = enqueue_step(c, c->cap_stream, ta, thermo, k);
+  for (int32_t k = 0; k < K && rc == MD_OK; ++k)
+    rc = enqueue_step(c, c->cap_stream, ta, thermo, k, energy_step_graph(ta, k, K));
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
   if (rc) {
@@ -829,7 +848,7 @@ md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
     if (rc) return rc;
   }
   for (; k < nsteps; ++k) {
-    md_status rc = enqueue_step(c, s, ta, thermo, k);
+    md_status rc = enqueue_step(c, s, ta, thermo, k, energy_step(ta, k, nsteps - 1));
     if (rc) return rc;
   }
   if (thermo) launch_apply_lambda(s, c->ntiles, c->tiles, c->stride, c->vel, c->lam, c->nrep);

@@ -174,13 +174,13 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   float4* pos16);
 // force.hip
 // mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
-// half kick v += dt/2 F/m before KE.
+// half kick v += dt/2 F/m before KE, and PE/W only when energy != 0.
 // unroll: list slots gathered per pipelined chunk (1, 2, 4 or 8).
-void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t tpp, int32_t unroll,
-                  int32_t ntiles, const Tile* tiles, const RepDesc* reps, const PairTab* tab,
-                  const double4* pos, const float4* pos16, double* vel, void* frc,
-                  const uint32_t* nbr, const int32_t* ncount, int32_t stride, int32_t cap,
-                  double dt, double* part, DevState* st);
+void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t energy, int32_t tpp,
+                  int32_t unroll, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
+                  const PairTab* tab, const double4* pos, const float4* pos16, double* vel,
+                  void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
+                  int32_t cap, double dt, double* part, DevState* st);
 // integrate.hip
 void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t ntiles,
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab,
@@ -211,10 +211,12 @@ void launch_reduce_chunks(hipStream_t s, int32_t nchunks, const RedChunk* ch, co
 // [fb0, fb1).  dmax holds the kick/drift tile maxima of |x - x_ref|^2
 // (tiles [tile0, tile1) of replica r), read when step = 1.
 // With part2 != NULL the per-replica pass reads the chunk results
-// part2[4 c + k], c in [cb0, cb1), instead of part and dmax.
+// part2[4 c + k], c in [cb0, cb1), instead of part and dmax.  energy = 0:
+// the step formed no PE/W; pe, virial, P and E keep their last values.
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
-                   const double* dmax, const double* part2, int32_t step, ThermoArgs ta,
-                   int64_t* kcall, double* lam, int32_t* rebuild, md_obs* obs, DevState* st);
+                   const double* dmax, const double* part2, int32_t step, int32_t energy,
+                   ThermoArgs ta, int64_t* kcall, double* lam, int32_t* rebuild, md_obs* obs,
+                   DevState* st);
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* obs,
                         DevState* st);
 void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam);
