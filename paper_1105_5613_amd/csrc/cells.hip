@@ -122,9 +122,12 @@ __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
                                                int32_t* __restrict__ img,
                                                int32_t* __restrict__ counts,
                                                int32_t* __restrict__ cell_of,
-                                               int32_t* __restrict__ slot, DevState* st) {
+                                               int32_t* __restrict__ slot, DevState* st,
+                                               int32_t ntiles, int32_t spread) {
   if (!st->any_rebuild) return;  // one flag load when nothing rebuilds
-  const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const int32_t lt = spread ? xcd_spread(blockIdx.x, spread) : xcd_block(blockIdx.x, gridDim.x);
+  if (lt >= ntiles) return;
+  const Tile t = tiles[lt];
   if (!rebuild[t.rep]) return;
   const int lane = threadIdx.x & 63;
   const int32_t i = t.start + threadIdx.x;
@@ -334,9 +337,12 @@ __global__ __launch_bounds__(kTile) void k_scatter(const Tile* __restrict__ tile
                                                    const int32_t* __restrict__ slot,
                                                    const int32_t* __restrict__ cell_start,
                                                    int32_t* __restrict__ tmp_src,
-                                                   const DevState* __restrict__ st) {
+                                                   const DevState* __restrict__ st,
+                                                   int32_t ntiles, int32_t spread) {
   if (!st->any_rebuild) return;
-  const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const int32_t lt = spread ? xcd_spread(blockIdx.x, spread) : xcd_block(blockIdx.x, gridDim.x);
+  if (lt >= ntiles) return;
+  const Tile t = tiles[lt];
   if (!rebuild[t.rep]) return;
   const int32_t i = t.start + threadIdx.x;
   if (i >= t.end) return;
@@ -430,8 +436,10 @@ void launch_zero_counts(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
 
 void launch_bin(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                 const int32_t* rebuild, double4* pos, const int32_t* id, int32_t* img,
-                int32_t* counts, int32_t* cell_of, int32_t* slot, DevState* st) {
-  k_bin<<<ntiles, kTile, 0, s>>>(tiles, reps, rebuild, pos, id, img, counts, cell_of, slot, st);
+                int32_t* counts, int32_t* cell_of, int32_t* slot, DevState* st, int32_t spread) {
+  const int32_t grid = spread ? spread_grid(ntiles, spread) : ntiles;
+  k_bin<<<grid, kTile, 0, s>>>(tiles, reps, rebuild, pos, id, img, counts, cell_of, slot, st,
+                               ntiles, spread);
 }
 
 size_t scan_bsum_elems(int32_t ncells) { return (size_t)nblk(ncells, kScanBlock) + 1; }
@@ -450,8 +458,10 @@ void launch_scan(hipStream_t s, int32_t ncells, const int32_t* counts, int32_t* 
 
 void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int32_t* rebuild,
                     const int32_t* cell_of, const int32_t* slot, const int32_t* cell_start,
-                    int32_t* tmp_src, const DevState* st) {
-  k_scatter<<<ntiles, kTile, 0, s>>>(tiles, rebuild, cell_of, slot, cell_start, tmp_src, st);
+                    int32_t* tmp_src, const DevState* st, int32_t spread) {
+  const int32_t grid = spread ? spread_grid(ntiles, spread) : ntiles;
+  k_scatter<<<grid, kTile, 0, s>>>(tiles, rebuild, cell_of, slot, cell_start, tmp_src, st,
+                                   ntiles, spread);
 }
 
 void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,

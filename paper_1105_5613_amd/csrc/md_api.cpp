@@ -200,11 +200,13 @@ md_status sync_and_check(md_ctx c) {
 
 void run_chain(md_ctx c, hipStream_t s) {
   launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
+  // several replicas rebuild at different steps: spread each one's blocks
+  const int32_t spread_t = c->nrep > 1 ? 4 : 0, spread_c = c->nrep > 1 ? 8 : 0;
   launch_bin(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->pos, c->id, c->img, c->counts,
-             c->cell_of, c->slot, c->st);
+             c->cell_of, c->slot, c->st, spread_t);
   launch_scan(s, c->ncells, c->counts, c->cell_start, c->bsum, c->st);
   launch_scatter(s, c->ntiles, c->tiles, c->rebuild, c->cell_of, c->slot, c->cell_start,
-                 c->tmp_src, c->st);
+                 c->tmp_src, c->st, spread_t);
   launch_cell_gather(s, c->ncells, c->cell_rep, c->rebuild, c->cell_start, c->tmp_src, c->stride,
                      c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp, c->st);
   if (c->cells)
@@ -214,12 +216,12 @@ void run_chain(md_ctx c, hipStream_t s) {
     launch_nlist_tiles(s, c->ncells, c->cell_rep, c->reps, c->rebuild, c->tab, c->thr_form,
                        c->cell_start,
                        c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
-                       c->xref, c->nbr16, c->ncount, c->st, c->cell_tile, c->rtiles);
+                       c->xref, c->nbr16, c->ncount, c->st, c->cell_tile, c->rtiles, spread_c);
   else
     launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->thr_form, c->cell_start,
                  c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
                  c->xref, c->nbr, c->ncount, c->st, c->ncells, c->cell_rep, c->any_single,
-                 c->any_multi, c->pos16);
+                 c->any_multi, c->pos16, spread_c);
 }
 
 // energy: form PE and W (the staged and list-free kernels always do).

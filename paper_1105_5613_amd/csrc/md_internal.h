@@ -117,6 +117,21 @@ __device__ inline int32_t xcd_block(int32_t b, int32_t nb) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// Block order of the rebuild chain in contexts with several replicas: the
+// work there is gated per replica, and xcd_block would put a rebuilding
+// replica's contiguous block range on one or two XCDs while the others idle.
+// Here groups of g consecutive logical blocks are dealt round-robin to the
+// XCDs instead (a group still shares an L2).  Bijective on a grid that is a
+// multiple of kXcd * g (spread_grid); logical blocks past the real count exit.
+__device__ inline int32_t xcd_spread(int32_t b, int32_t g) {
+  const int32_t x = b % kXcd, k = b / kXcd;
+  return ((k / g) * kXcd + x) * g + (k % g);
+}
+inline int32_t spread_grid(int32_t nb, int32_t g) {
+  const int32_t m = kXcd * g;
+  return (nb + m - 1) / m * m;
+}
+
 struct DevState {      // context scalars the kernels update
   int32_t err;
   int32_t any_rebuild;
@@ -137,13 +152,13 @@ void launch_zero_counts(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* rebuild, const DevState* st, int32_t* counts);
 void launch_bin(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                 const int32_t* rebuild, double4* pos, const int32_t* id, int32_t* img,
-                int32_t* counts, int32_t* cell_of, int32_t* slot, DevState* st);
+                int32_t* counts, int32_t* cell_of, int32_t* slot, DevState* st, int32_t spread);
 void launch_scan(hipStream_t s, int32_t ncells, const int32_t* counts, int32_t* cell_start,
                  int32_t* bsum, const DevState* st);
 size_t scan_bsum_elems(int32_t ncells);
 void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int32_t* rebuild,
                     const int32_t* cell_of, const int32_t* slot, const int32_t* cell_start,
-                    int32_t* tmp_src, const DevState* st);
+                    int32_t* tmp_src, const DevState* st, int32_t spread);
 void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* rebuild, const int32_t* cell_start,
                         const int32_t* tmp_src, int32_t stride, const int32_t* id,
@@ -171,7 +186,7 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   double4* pos, double* vel, int32_t* id, double* xref,
                   uint32_t* nbr, int32_t* ncount, DevState* st, int32_t ncells,
                   const int32_t* cell_rep, int32_t any_single, int32_t any_multi,
-                  float4* pos16);
+                  float4* pos16, int32_t spread);
 // force.hip
 // mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
 // half kick v += dt/2 F/m before KE, and PE/W only when energy != 0.
@@ -245,7 +260,7 @@ void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
                         int32_t* ncount, DevState* st, const int32_t* cell_tile,
-                        const RowTile* rtiles);
+                        const RowTile* rtiles, int32_t spread);
 void launch_decode_staged(hipStream_t s, int32_t nrt, const RowTile* rtiles, const RepDesc* reps,
                           const int32_t* cell_start, int32_t cap, const uint16_t* nbr,
                           const int32_t* ncount, uint32_t* out);

@@ -204,7 +204,8 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
     int32_t* __restrict__ id, double* __restrict__ xref,
     typename std::conditional<TILE, uint16_t, uint32_t>::type* __restrict__ nbr,
     int32_t* __restrict__ ncount, DevState* st, float4* __restrict__ pos16,
-    const int32_t* __restrict__ cell_tile, const RowTile* __restrict__ rtiles, int32_t dcode) {
+    const int32_t* __restrict__ cell_tile, const RowTile* __restrict__ rtiles, int32_t dcode,
+    int32_t spread) {
   using E = typename std::conditional<TILE, uint16_t, uint32_t>::type;
   __shared__ double s_thr[16];
   __shared__ int32_t s_pre[4][28];    // first packed candidate of piece p
@@ -217,7 +218,8 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t c = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+  const int32_t c =
+      (spread ? xcd_spread(blockIdx.x, spread) : xcd_block(blockIdx.x, gridDim.x)) * 4 + w;
   if (c >= ncells) return;
   const int32_t r = cell_rep[c];
   if (!rebuild[r]) return;
@@ -420,15 +422,16 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                   double4* pos, double* vel, int32_t* id, double* xref, uint32_t* nbr,
                   int32_t* ncount, DevState* st, int32_t ncells, const int32_t* cell_rep,
-                  int32_t any_single, int32_t any_multi, float4* pos16) {
+                  int32_t any_single, int32_t any_multi, float4* pos16, int32_t spread) {
   // mixed lists (records present) carry cell offsets instead of images
   const int32_t dcode = pos16 != nullptr;
   if (any_multi) {
+    const int32_t nb = (ncells + 3) / 4, grid = spread ? spread_grid(nb, spread) : nb;
 #define KN(NT)                                                                             \
   k_nlist_cells<kCwHomes, kCwBuf, false, NT>                                               \
-      <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                       \
+      <<<grid, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                                   \
           ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, \
-          id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr, dcode)
+          id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr, dcode, spread)
     if (thr_form == 2) KN(2); else KN(4);
 #undef KN
   }
@@ -443,12 +446,13 @@ void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
                         int32_t* ncount, DevState* st, const int32_t* cell_tile,
-                        const RowTile* rtiles) {
+                        const RowTile* rtiles, int32_t spread) {
+  const int32_t nb = (ncells + 3) / 4, grid = spread ? spread_grid(nb, spread) : nb;
 #define KT(NT)                                                                                   \
   k_nlist_cells<kCwHomes, kCwBuf, true, NT>                                                      \
-      <<<(ncells + 3) / 4, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                             \
+      <<<grid, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                                         \
           ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, id_tmp, \
-          pos, vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles, 0)
+          pos, vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles, 0, spread)
   if (thr_form == 2) KT(2); else KT(4);
 #undef KT
 }
