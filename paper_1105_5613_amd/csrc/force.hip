@@ -135,13 +135,14 @@ __global__ __launch_bounds__(kTile) void k_force(
     n = n < cap ? n : cap;
     const uint32_t* row = nbr + list_base(i, cap);
     // entries are fetched one chunk of U ahead; slots past n point at the
-    // particle itself and are masked out
+    // particle itself and are masked out.  The list is read once per launch:
+    // non-temporal loads keep it from evicting neighbour records from the L2
     const uint32_t self = (uint32_t)i;
     uint32_t e[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t k = lane_p + u * TPP;
-      e[u] = k < n ? row[(size_t)k * kSlice] : self;
+      e[u] = k < n ? __builtin_nontemporal_load(row + (size_t)k * kSlice) : self;
     }
     if constexpr (MIXED) {
       // 16-byte cell-relative records (see make_rec16)
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(kTile) void k_force(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t k = k0 + (U + u) * TPP;
-          en[u] = k < n ? row[(size_t)k * kSlice] : self;
+          en[u] = k < n ? __builtin_nontemporal_load(row + (size_t)k * kSlice) : self;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(kTile) void k_force(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t k = k0 + (U + u) * TPP;
-          en[u] = k < n ? row[(size_t)k * kSlice] : self;
+          en[u] = k < n ? __builtin_nontemporal_load(row + (size_t)k * kSlice) : self;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
