@@ -90,9 +90,21 @@ __device__ inline void block_sum3(double& a, double& b, double& c) {
   }
 }
 
+// List entry k of a row.  NTL (a list larger than the last-level cache
+// could hold): non-temporal loads, so the entries streamed once per launch
+// do not evict the neighbour records from the L2.  A list that fits stays
+// cached from one launch to the next and is read normally.
+template <bool NTL>
+__device__ inline uint32_t list_entry(const uint32_t* p) {
+  if constexpr (NTL)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
 // EN = false (in-step launches on steps whose observables are not read):
 // the per-pair energy and virial terms are skipped and their partials are 0.
-template <bool MIXED, int MODE, int TPP, int U, bool EN>
+template <bool MIXED, int MODE, int TPP, int U, bool EN, bool NTL>
 __global__ __launch_bounds__(kTile) void k_force(
     const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
     const PairTab* __restrict__ tab, const double4* __restrict__ pos,
@@ -135,14 +147,13 @@ __global__ __launch_bounds__(kTile) void k_force(
     n = n < cap ? n : cap;
     const uint32_t* row = nbr + list_base(i, cap);
     // entries are fetched one chunk of U ahead; slots past n point at the
-    // particle itself and are masked out.  The list is read once per launch:
-    // non-temporal loads keep it from evicting neighbour records from the L2
+    // particle itself and are masked out
     const uint32_t self = (uint32_t)i;
     uint32_t e[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t k = lane_p + u * TPP;
-      e[u] = k < n ? __builtin_nontemporal_load(row + (size_t)k * kSlice) : self;
+      e[u] = k < n ? list_entry<NTL>(row + (size_t)k * kSlice) : self;
     }
     if constexpr (MIXED) {
       // 16-byte cell-relative records (see make_rec16)
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(kTile) void k_force(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t k = k0 + (U + u) * TPP;
-          en[u] = k < n ? __builtin_nontemporal_load(row + (size_t)k * kSlice) : self;
+          en[u] = k < n ? list_entry<NTL>(row + (size_t)k * kSlice) : self;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -197,7 +208,7 @@ __global__ __launch_bounds__(kTile) void k_force(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t k = k0 + (U + u) * TPP;
-          en[u] = k < n ? __builtin_nontemporal_load(row + (size_t)k * kSlice) : self;
+          en[u] = k < n ? list_entry<NTL>(row + (size_t)k * kSlice) : self;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -273,13 +284,13 @@ __global__ __launch_bounds__(kTile) void k_force(
   }
 }
 
-template <bool MIXED, int MODE, bool EN>
+template <bool MIXED, int MODE, bool EN, bool NTL>
 void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const Tile* tiles,
               const RepDesc* reps, const PairTab* tab, const double4* pos, const float4* pos16,
               double* vel, void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
               int32_t cap, double dt, double* part, DevState* st) {
 #define KF(TPP, U)                                                                       \
-  k_force<MIXED, MODE, TPP, U, EN><<<ntiles * TPP, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, \
+  k_force<MIXED, MODE, TPP, U, EN, NTL><<<ntiles * TPP, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, \
                                                               vel, frc, nbr, ncount, stride, \
                                                               cap, dt, part, st)
   const int key = tpp * 16 + unroll;
@@ -302,25 +313,29 @@ void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const 
 
 // Partials: one FP64 triple (pe, w, ke) per logical block; with tpp lanes
 // per particle, tile t owns logical blocks [t*tpp, (t+1)*tpp).
-void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t energy, int32_t tpp,
+void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t energy,
+                  int32_t stream_list, int32_t tpp,
                   int32_t unroll, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                   const PairTab* tab, const double4* pos, const float4* pos16, double* vel,
                   void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
                   int32_t cap, double dt, double* part, DevState* st) {
-#define LT(M, MO, EN)                                                                    \
-  launch_t<M, MO, EN>(s, tpp, unroll, ntiles, tiles, reps, tab, pos, pos16, vel, frc, nbr, \
-                      ncount, stride, cap, dt, part, st)
+#define LT1(M, MO, EN, NTL)                                                                  \
+  launch_t<M, MO, EN, NTL>(s, tpp, unroll, ntiles, tiles, reps, tab, pos, pos16, vel, frc, nbr, \
+                           ncount, stride, cap, dt, part, st)
+#define LT(M, MO, EN) \
+  if (stream_list) LT1(M, MO, EN, true); else LT1(M, MO, EN, false)
   // mode 0 (a plain force evaluation) always forms the energies
   if (mixed) {
-    if (mode == 0) LT(true, 0, true);
-    else if (energy) LT(true, 1, true);
-    else LT(true, 1, false);
+    if (mode == 0) { LT(true, 0, true); }
+    else if (energy) { LT(true, 1, true); }
+    else { LT(true, 1, false); }
   } else {
-    if (mode == 0) LT(false, 0, true);
-    else if (energy) LT(false, 1, true);
-    else LT(false, 1, false);
+    if (mode == 0) { LT(false, 0, true); }
+    else if (energy) { LT(false, 1, true); }
+    else { LT(false, 1, false); }
   }
 #undef LT
+#undef LT1
 }
 
 }  // namespace mdk

@@ -113,14 +113,14 @@ __global__ __launch_bounds__(kStageHomes* TPP) void k_force_staged(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t k = lane_p + u * TPP;
-      e[u] = k < n ? (uint32_t)__builtin_nontemporal_load(row + (size_t)k * kSlice) : 0u;
+      e[u] = k < n ? (uint32_t)row[(size_t)k * kSlice] : 0u;
     }
     for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
       uint32_t en[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int32_t k = k0 + (U + u) * TPP;
-        en[u] = k < n ? (uint32_t)__builtin_nontemporal_load(row + (size_t)k * kSlice) : 0u;
+        en[u] = k < n ? (uint32_t)row[(size_t)k * kSlice] : 0u;
       }
       double qx[U], qy[U], qz[U];
 #pragma unroll

@@ -35,6 +35,7 @@ struct md_ctx_s {
   PairTab* tab = nullptr;
   int32_t thr_form = 4;  // form of the list thresholds in the neighbour search (fma_pair_form)
   int32_t rc2_form = 4;  // form of the force cutoffs on the list-free path
+  int32_t nmax_rep = 0;  // particles of the largest replica
   DevState* st = nullptr;
   int32_t *cell_rep = nullptr, *counts = nullptr, *cell_start = nullptr, *bsum = nullptr;
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp_src = nullptr;
@@ -235,9 +236,10 @@ void launch_forces(md_ctx c, int32_t mode, hipStream_t s, int32_t energy = 1) {
                         c->tab, c->cell_start, c->pos, c->vel, c->frc, c->nbr16, c->ncount,
                         c->stride, c->cap, c->lcap_f, c->p.dt, c->part, c->st);
   else
-    launch_force(s, c->mixed, mode, energy, c->tpp, c->unroll, c->ntiles, c->tiles, c->reps,
-                 c->tab, c->pos, c->pos16, c->vel, c->frc, c->nbr, c->ncount, c->stride, c->cap,
-                 c->p.dt, c->part, c->st);
+    launch_force(s, c->mixed, mode, energy,
+                 (size_t)c->nmax_rep * c->cap * sizeof(uint32_t) > kStreamListBytes, c->tpp,
+                 c->unroll, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16, c->vel,
+                 c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st);
 }
 
 md_status grow_capacity(md_ctx c) {
@@ -453,6 +455,7 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
   c->unroll = p->unroll == 0 ? 4 : p->unroll;
   c->stream = (hipStream_t)hip_stream;
   if (alloc) c->alloc = *alloc;
+  for (int r = 0; r < nrep; ++r) c->nmax_rep = std::max<int32_t>(c->nmax_rep, (int32_t)n[r]);
 
   // replica geometry: cells of side >= max rc + skin (nc < 3 -> one cell)
   const double side = rcmax + p->skin;
