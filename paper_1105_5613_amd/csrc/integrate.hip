@@ -24,12 +24,16 @@ __global__ __launch_bounds__(kTile) void k_kick_drift(
     double* __restrict__ vel, const FT* __restrict__ frc, const double* __restrict__ xref,
     int32_t stride, double dt,
     const double* __restrict__ lam, int32_t* __restrict__ rebuild,
-    double* __restrict__ dmax, DevState* st) {
+    double* __restrict__ dmax, DevState* st, int32_t* __restrict__ counts, int32_t nzero) {
   __shared__ double s_im[4];
   __shared__ double s_red[kTile / 64];
   if (threadIdx.x < 4) s_im[threadIdx.x] = tab->inv_mass[threadIdx.x];
   __syncthreads();
   const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
+  // one replica: the cell histogram is only read inside a rebuild, so it is
+  // cleared here every step instead of by a separate gated launch
+  const int32_t gz = blockIdx.x * kTile + threadIdx.x;
+  if (gz < nzero) counts[gz] = 0;
   const Tile t = tiles[tb];
   const int32_t i = t.start + threadIdx.x;
   double d2 = 0.0;
@@ -243,11 +247,11 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab, double4* pos,
                        float4* pos16, double* vel, const void* frc, const double* xref,
                        int32_t stride, double dt, const double* lam, int32_t* rebuild,
-                       double* dmax, DevState* st) {
+                       double* dmax, DevState* st, int32_t* counts, int32_t nzero) {
 #define KD(FT, TH)                                                                         \
   k_kick_drift<FT, TH><<<ntiles, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, vel,         \
                                                 (const FT*)frc, xref, stride, dt, lam,     \
-                                                rebuild, dmax, st)
+                                                rebuild, dmax, st, counts, nzero)
   if (mixed) {
     if (thermo) KD(float, true); else KD(float, false);
   } else {

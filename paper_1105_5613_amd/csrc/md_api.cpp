@@ -199,8 +199,10 @@ md_status sync_and_check(md_ctx c) {
   return MD_OK;
 }
 
-void run_chain(md_ctx c, hipStream_t s) {
-  launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
+// zeroed: the kick of this step already cleared the cell histogram (one
+// replica, see launch_kick_drift's nzero)
+void run_chain(md_ctx c, hipStream_t s, bool zeroed = false) {
+  if (!zeroed) launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
   // several replicas rebuild at different steps: spread each one's blocks
   const int32_t spread_t = c->nrep > 1 ? 4 : 0, spread_c = c->nrep > 1 ? 8 : 0;
   launch_bin(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->pos, c->id, c->img, c->counts,
@@ -335,10 +337,14 @@ void launch_forces0(md_ctx c) {
 // energy: the step forms PE and W (the observables refreshed on it).
 md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t thermo, int32_t k,
                        int32_t energy) {
+  // one replica: its histogram is read only inside a rebuild, so the kick
+  // clears it when its threads cover the cells (not in very dilute boxes)
+  // and the chain skips a launch
+  const bool zero_in_kick = c->nrep == 1 && (int64_t)c->ncells <= (int64_t)c->ntiles * kTile;
   launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16,
                     c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->dmax,
-                    c->st);
-  run_chain(c, s);
+                    c->st, c->counts, zero_in_kick ? c->ncells : 0);
+  run_chain(c, s, zero_in_kick);
   const bool timed = c->prof_every > 0 && (k + 1) % c->prof_every == 0;
   if (timed) {
     if (c->ev_pool.size() < c->ev_used + 2) return fail(c, MD_EHIP, "event pool exhausted");

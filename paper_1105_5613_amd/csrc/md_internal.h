@@ -214,7 +214,8 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab,
                        double4* pos, float4* pos16, double* vel, const void* frc,
                        const double* xref, int32_t stride, double dt, const double* lam,
-                       int32_t* rebuild, double* dmax, DevState* st);
+                       int32_t* rebuild, double* dmax, DevState* st, int32_t* counts,
+                       int32_t nzero);
 struct ThermoArgs {
   const double* T0;    // [nrep]
   const double* T1;    // [nrep]

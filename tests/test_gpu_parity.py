@@ -189,6 +189,30 @@ def test_list_threshold_ties(torch_cuda, precision, path):
     assert 0 < count.sum() < n  # some pairs in, some out
 
 
+def test_dilute_box_cells_after_steps(torch_cuda):
+    """512 particles on a jittered lattice in a 60-sigma box: 9,261 cells,
+    more than the threads of the kick kernel, so the cell histogram is cleared
+    by its own launch.  Cells and lists bit-exact after several rebuilds."""
+    from paper_1105_5613_amd import System
+    say("case dilute box")
+    n, L = 512, 60.0
+    g = (np.arange(8) + 0.5) * (L / 8)
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    rng = np.random.default_rng(14)
+    x = x + rng.uniform(-1.0, 1.0, x.shape)
+    v = rng.normal(0.0, math.sqrt(2.0), x.shape)
+    v -= v.mean(axis=0)
+    types = (rng.random(n) < 0.2).astype(np.int32)
+    sysm = System(lib_params(), [n], [L])
+    sysm.set_state(x, v, types)
+    assert sysm.replica_info(0)["nc"] == 21
+    sysm.step(200)
+    assert sysm.observables()[0]["n_rebuild"] >= 3
+    xs = sysm.get_state()[0].cpu().numpy()
+    sysm.build_cells()
+    compare_cells_lists(sysm, oracle_params(), xs, types, L, tag="dilute")
+
+
 # Species tables beyond the binary mixture.  The list test forms the pair
 # threshold either as one FMA over the home species value (one species, or two
 # whose thresholds for each partner species lie within a factor of two) or by
