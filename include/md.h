@@ -101,6 +101,11 @@ typedef struct {
   int32_t tile_cells;    /* staged path: cells per row tile (1..64); 0 = auto */
   int32_t stage_slots;   /* staged path: LDS slots per tile (>= 64); slots beyond are
                             read from global memory; 0 = auto */
+  int32_t split_kick;    /* 0 = auto: in directly launched NVE steps of a one-replica
+                            context on the gather path, the force launch of a step also
+                            applies the next step's first half kick and drift (same
+                            arithmetic, one pass over the particles fewer per step);
+                            1 = always a separate kick/drift launch */
 } md_params;
 
 /* Per-replica observables after the last completed step. */

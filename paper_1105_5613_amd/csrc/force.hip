@@ -102,6 +102,44 @@ __device__ inline uint32_t list_entry(const uint32_t* p) {
     return *p;
 }
 
+// Block reduction of (sum, sum, sum, max); results valid in thread 0.
+__device__ inline void block_sum3_max(double& a, double& b, double& c, double& m) {
+  __shared__ double red[4][kTile / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmax(m, __shfl_xor(m, d, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+    red[2][w] = c;
+    red[3][w] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = red[0][0];
+    b = red[1][0];
+    c = red[2][0];
+    m = red[3][0];
+    for (int k = 1; k < kTile / 64; ++k) {
+      a += red[0][k];
+      b += red[1][k];
+      c += red[2][k];
+      m = fmax(m, red[3][k]);
+    }
+  }
+}
+
+// MODE 0: forces only.  MODE 1: forces and the step's second half kick.
+// MODE 2 (NVE, one replica): as MODE 1, then the next step's first half kick
+// and drift with the same arithmetic as k_kick_drift; the drifted positions
+// go to pos_out / pos16_out (the other buffer of a pair: the neighbour
+// records of this launch are read from pos / pos16), the forces are not
+// stored (the next kick has used them), the largest squared displacement
+// from xref per logical block goes to the fourth partial, and the cell
+// histogram of the next rebuild is cleared (nzero cells).
 // EN = false (in-step launches on steps whose observables are not read):
 // the per-pair energy and virial terms are skipped and their partials are 0.
 template <bool MIXED, int MODE, int TPP, int U, bool EN, bool NTL>
@@ -110,13 +148,20 @@ __global__ __launch_bounds__(kTile) void k_force(
     const PairTab* __restrict__ tab, const double4* __restrict__ pos,
     const float4* __restrict__ pos16, double* __restrict__ vel, void* __restrict__ frc_,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncount, int32_t stride,
-    int32_t cap, double dt, double* __restrict__ part, DevState* st) {
+    int32_t cap, double dt, double* __restrict__ part, DevState* st, FuseOut fo) {
   using T = typename std::conditional<MIXED, float, double>::type;
   __shared__ PairLds<T> P;
-  __shared__ double s_mass[4];
+  __shared__ double s_mass[4], s_im[4];
   __shared__ float4 s_doff[64];  // mixed: d * cell side for each entry code
   load_pair<T>(P, tab);
-  if (threadIdx.x < 4) s_mass[threadIdx.x] = tab->mass[threadIdx.x];
+  if (threadIdx.x < 4) {
+    s_mass[threadIdx.x] = tab->mass[threadIdx.x];
+    s_im[threadIdx.x] = tab->inv_mass[threadIdx.x];
+  }
+  if constexpr (MODE == 2) {
+    const int32_t gz = blockIdx.x * kTile + threadIdx.x;
+    if (gz < fo.nzero) fo.counts[gz] = 0;
+  }
 
   // with TPP lanes per particle a block covers kTile / TPP particles; a tile
   // of kTile particles takes TPP consecutive (logical) blocks
@@ -142,6 +187,7 @@ __global__ __launch_bounds__(kTile) void k_force(
   T fx = 0, fy = 0, fz = 0;
   T pe_i = 0, w_i = 0;
   int32_t ti = 0;
+  uint32_t wbits = 0;  // mixed: the home record's species and cell code
   if (active) {
     int32_t n = ncount[i];
     n = n < cap ? n : cap;
@@ -158,7 +204,8 @@ __global__ __launch_bounds__(kTile) void k_force(
     if constexpr (MIXED) {
       // 16-byte cell-relative records (see make_rec16)
       const float4 pi = pos16[i];
-      ti = (int32_t)(__float_as_uint(pi.w) >> 30);
+      wbits = __float_as_uint(pi.w);
+      ti = (int32_t)(wbits >> 30);
       for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
         float4 q[U];
 #pragma unroll
@@ -254,33 +301,58 @@ __global__ __launch_bounds__(kTile) void k_force(
       w_i += __shfl_xor(w_i, d, 64);
     }
   }
+  double d2 = 0.0;
   if (active && lane_p == 0) {
     if (!isfinite((double)(fx + fy + fz))) atomicOr(&st->err, kErrNonFinite);
-    T* frc = (T*)frc_;
-    frc[i] = fx;
-    frc[stride + i] = fy;
-    frc[2 * (size_t)stride + i] = fz;
+    if constexpr (MODE != 2) {
+      T* frc = (T*)frc_;
+      frc[i] = fx;
+      frc[stride + i] = fy;
+      frc[2 * (size_t)stride + i] = fz;
+    }
     pe = 0.5 * (double)pe_i;
     w = 0.5 * (double)w_i;
     const double m = s_mass[ti];
     double v0 = vel[i], v1 = vel[stride + i], v2 = vel[2 * (size_t)stride + i];
-    if (MODE == 1) {
+    if (MODE >= 1) {
       const double hm = 0.5 * dt / m;
       v0 += hm * (double)fx;
       v1 += hm * (double)fy;
       v2 += hm * (double)fz;
+    }
+    ke = 0.5 * m * (v0 * v0 + v1 * v1 + v2 * v2);
+    if constexpr (MODE == 2) {
+      // the next step's first half kick and drift
+      double4 p = pos[i];
+      const double hk = 0.5 * dt * s_im[(int32_t)p.w];
+      v0 += hk * (double)fx;
+      v1 += hk * (double)fy;
+      v2 += hk * (double)fz;
+      p.x += dt * v0;
+      p.y += dt * v1;
+      p.z += dt * v2;
+      fo.pos_out[i] = p;
+      if constexpr (MIXED) fo.pos16_out[i] = make_rec16(p.x, p.y, p.z, wbits, Rp.cside);
+      const double e0 = p.x - fo.xref[i], e1 = p.y - fo.xref[stride + i],
+                   e2 = p.z - fo.xref[2 * (size_t)stride + i];
+      d2 = e0 * e0 + e1 * e1 + e2 * e2;
+    }
+    if (MODE >= 1) {
       vel[i] = v0;
       vel[stride + i] = v1;
       vel[2 * (size_t)stride + i] = v2;
     }
-    ke = 0.5 * m * (v0 * v0 + v1 * v1 + v2 * v2);
   }
-  block_sum3(pe, w, ke);
+  if constexpr (MODE == 2)
+    block_sum3_max(pe, w, ke, d2);
+  else
+    block_sum3(pe, w, ke);
   if (threadIdx.x == 0) {
     double* o = part + 4 * (size_t)lb;
     o[0] = pe;
     o[1] = w;
     o[2] = ke;
+    if (MODE == 2) o[3] = d2;
   }
 }
 
@@ -288,11 +360,11 @@ template <bool MIXED, int MODE, bool EN, bool NTL>
 void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const Tile* tiles,
               const RepDesc* reps, const PairTab* tab, const double4* pos, const float4* pos16,
               double* vel, void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
-              int32_t cap, double dt, double* part, DevState* st) {
+              int32_t cap, double dt, double* part, DevState* st, const FuseOut& fo) {
 #define KF(TPP, U)                                                                       \
   k_force<MIXED, MODE, TPP, U, EN, NTL><<<ntiles * TPP, kTile, 0, s>>>(tiles, reps, tab, pos, pos16, \
                                                               vel, frc, nbr, ncount, stride, \
-                                                              cap, dt, part, st)
+                                                              cap, dt, part, st, fo)
   const int key = tpp * 16 + unroll;
   switch (key) {
     case 1 * 16 + 1: KF(1, 1); break;
@@ -318,19 +390,21 @@ void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t energy,
                   int32_t unroll, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                   const PairTab* tab, const double4* pos, const float4* pos16, double* vel,
                   void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
-                  int32_t cap, double dt, double* part, DevState* st) {
+                  int32_t cap, double dt, double* part, DevState* st, const FuseOut& fo) {
 #define LT1(M, MO, EN, NTL)                                                                  \
   launch_t<M, MO, EN, NTL>(s, tpp, unroll, ntiles, tiles, reps, tab, pos, pos16, vel, frc, nbr, \
-                           ncount, stride, cap, dt, part, st)
+                           ncount, stride, cap, dt, part, st, fo)
 #define LT(M, MO, EN) \
   if (stream_list) LT1(M, MO, EN, true); else LT1(M, MO, EN, false)
   // mode 0 (a plain force evaluation) always forms the energies
   if (mixed) {
     if (mode == 0) { LT(true, 0, true); }
+    else if (mode == 2) { if (energy) { LT(true, 2, true); } else { LT(true, 2, false); } }
     else if (energy) { LT(true, 1, true); }
     else { LT(true, 1, false); }
   } else {
     if (mode == 0) { LT(false, 0, true); }
+    else if (mode == 2) { if (energy) { LT(false, 2, true); } else { LT(false, 2, false); } }
     else if (energy) { LT(false, 1, true); }
     else { LT(false, 1, false); }
   }

@@ -95,35 +95,41 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
                                                         const double* __restrict__ dmax,
                                                         const double* __restrict__ part2,
                                                         int32_t step, int32_t energy,
-                                                        ThermoArgs ta,
+                                                        DriftArgs drift, ThermoArgs ta,
                                                         int64_t* __restrict__ kcall,
                                                         double* __restrict__ lam,
                                                         int32_t* __restrict__ rebuild,
                                                         md_obs* __restrict__ obs, DevState* st) {
-  __shared__ double red[4][kRedThreads];
+  __shared__ double red[5][kRedThreads];
   const int32_t r = blockIdx.x;
   const RepDesc R = reps[r];
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
-  double m = 0.0;  // largest squared displacement of this step's drift
+  double m = 0.0;   // largest squared displacement of this step's drift
+  double mn = 0.0;  // ... of the next step's drift (fused force launch)
   if (part2) {
     for (int32_t b = R.cb0 + threadIdx.x; b < R.cb1; b += kRedThreads) {
-      for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part2[4 * (size_t)b + k]);
-      m = fmax(m, part2[4 * (size_t)b + 3]);
+      for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part2[kPart2 * (size_t)b + k]);
+      m = fmax(m, part2[kPart2 * (size_t)b + 3]);
+      mn = fmax(mn, part2[kPart2 * (size_t)b + 4]);
     }
   } else {
-    for (int32_t b = R.fb0 + threadIdx.x; b < R.fb1; b += kRedThreads)
+    for (int32_t b = R.fb0 + threadIdx.x; b < R.fb1; b += kRedThreads) {
       for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
-    if (step)
+      if (drift.next) mn = fmax(mn, part[4 * (size_t)b + 3]);
+    }
+    if (step && drift.src == 0)
       for (int32_t b = R.tile0 + threadIdx.x; b < R.tile1; b += kRedThreads)
         m = fmax(m, dmax[b]);
   }
   for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
   red[3][threadIdx.x] = m;
+  red[4][threadIdx.x] = mn;
   __syncthreads();
   for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
     if (threadIdx.x < h) {
       for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
       red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + h]);
+      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + h]);
     }
     __syncthreads();
   }
@@ -136,7 +142,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
     o.virial = w;
   }
   o.T_target = 0.0;
-  if (step) o.max_disp = sqrt(red[3][0]);
+  if (step) o.max_disp = sqrt(drift.src ? drift.pend[r] : red[3][0]);
   if (step) {
     const int64_t k = ++kcall[r];
     if (ta.thermo) {
@@ -154,11 +160,18 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
       o.T_target = tt;
     }
     o.step += 1;
-    if (rebuild[r]) {
-      o.n_rebuild += 1;
+    if (rebuild[r]) o.n_rebuild += 1;
+    if (drift.next) {
+      // the next step's positions are drifted already: its rebuild decision
+      const double mx = red[4][0];
+      const int32_t nb = mx > R.half_skin2 ? 1 : 0;
+      drift.pend[r] = mx;
+      rebuild[r] = nb;
+      st->any_rebuild = nb;
+    } else {
       rebuild[r] = 0;
+      if (r == 0) st->any_rebuild = 0;
     }
-    if (r == 0) st->any_rebuild = 0;
   }
   o.ke = ke;
   o.T = 2.0 * ke / R.dof;
@@ -181,27 +194,32 @@ constexpr int kChunkThreads = 256;
 __global__ __launch_bounds__(kChunkThreads) void k_reduce_chunks(const RedChunk* __restrict__ ch,
                                                                  const double* __restrict__ part,
                                                                  const double* __restrict__ dmax,
-                                                                 int32_t step,
+                                                                 int32_t step, int32_t next,
                                                                  double* __restrict__ part2) {
-  __shared__ double red[4][kChunkThreads];
+  __shared__ double red[5][kChunkThreads];
   const RedChunk C = ch[blockIdx.x];
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
-  for (int32_t b = C.b0 + threadIdx.x; b < C.b1; b += kChunkThreads)
+  double mn = 0.0;
+  for (int32_t b = C.b0 + threadIdx.x; b < C.b1; b += kChunkThreads) {
     for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
+    if (next) mn = fmax(mn, part[4 * (size_t)b + 3]);
+  }
   double m = 0.0;
   if (step)
     for (int32_t t = C.t0 + threadIdx.x; t < C.t1; t += kChunkThreads) m = fmax(m, dmax[t]);
   for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
   red[3][threadIdx.x] = m;
+  red[4][threadIdx.x] = mn;
   __syncthreads();
   for (int h = kChunkThreads / 2; h >= 1; h >>= 1) {
     if (threadIdx.x < h) {
       for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
       red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + h]);
+      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + h]);
     }
     __syncthreads();
   }
-  if (threadIdx.x < 4) part2[4 * (size_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 5) part2[kPart2 * (size_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
 __global__ void k_after_build(int32_t nrep, int32_t* rebuild, md_obs* obs, DevState* st) {
@@ -262,15 +280,15 @@ void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t nti
 
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
                    const double* dmax, const double* part2, int32_t step, int32_t energy,
-                   ThermoArgs ta, int64_t* kcall, double* lam, int32_t* rebuild, md_obs* obs,
-                   DevState* st) {
-  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, dmax, part2, step, energy, ta, kcall, lam,
-                                        rebuild, obs, st);
+                   DriftArgs drift, ThermoArgs ta, int64_t* kcall, double* lam, int32_t* rebuild,
+                   md_obs* obs, DevState* st) {
+  k_reduce<<<nrep, kRedThreads, 0, s>>>(reps, part, dmax, part2, step, energy, drift, ta, kcall,
+                                        lam, rebuild, obs, st);
 }
 
 void launch_reduce_chunks(hipStream_t s, int32_t nchunks, const RedChunk* ch, const double* part,
-                          const double* dmax, int32_t step, double* part2) {
-  k_reduce_chunks<<<nchunks, kChunkThreads, 0, s>>>(ch, part, dmax, step, part2);
+                          const double* dmax, int32_t step, int32_t next, double* part2) {
+  k_reduce_chunks<<<nchunks, kChunkThreads, 0, s>>>(ch, part, dmax, step, next, part2);
 }
 
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* obs,

@@ -49,6 +49,12 @@ struct md_ctx_s {
   double* part = nullptr;
   int32_t* rebuild = nullptr;
   double* dmax = nullptr;   // [ntiles] per-tile max of the last drift
+  // fused NVE steps (force mode 2): the drifted positions go to the other
+  // buffer of a pair, pos <-> pos_tmp (pos_tmp is scratch of the rebuild
+  // chain otherwise) and pos16 <-> pos16_alt; dpend [nrep] holds the drift
+  // maximum measured for the next step
+  float4* pos16_alt = nullptr;
+  double* dpend = nullptr;
   // two-level reduction of the force partials (large replicas only)
   std::vector<RedChunk> chunks_h;
   RedChunk* chunks = nullptr;
@@ -68,7 +74,7 @@ struct md_ctx_s {
   // captured K-step graphs (md_params.graph_steps)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int64_t gkey[10] = {0};
+  int64_t gkey[11] = {0};
   int32_t prof_epoch = 0;
   // force-kernel timing
   int32_t prof_every = 0;
@@ -179,6 +185,7 @@ md_status validate(const md_params* p, std::string* why) {
   if (p->tile_cells < 0 || p->tile_cells > kMaxRowCells)
     return *why = "tile_cells must be 0..64", MD_EINVAL;
   if (p->stage_slots != 0 && p->stage_slots < 64) return *why = "stage_slots must be 0 or >= 64", MD_EINVAL;
+  if (p->split_kick != 0 && p->split_kick != 1) return *why = "split_kick must be 0 or 1", MD_EINVAL;
   return MD_OK;
 }
 
@@ -228,7 +235,10 @@ void run_chain(md_ctx c, hipStream_t s, bool zeroed = false) {
 }
 
 // energy: form PE and W (the staged and list-free kernels always do).
-void launch_forces(md_ctx c, int32_t mode, hipStream_t s, int32_t energy = 1) {
+// mode 2 (gather path only): the fused NVE step, see FuseOut; the caller
+// swaps the position buffers after the launch.
+void launch_forces(md_ctx c, int32_t mode, hipStream_t s, int32_t energy = 1,
+                   int32_t nzero = 0) {
   if (c->cells)
     launch_force_cells(s, c->mixed, mode, c->rc2_form, c->nrt, c->rtiles, c->reps, c->tab,
                        c->cell_start, c->pos, c->vel, c->frc, c->stride, c->p.dt, c->part,
@@ -241,7 +251,8 @@ void launch_forces(md_ctx c, int32_t mode, hipStream_t s, int32_t energy = 1) {
     launch_force(s, c->mixed, mode, energy,
                  (size_t)c->nmax_rep * c->cap * sizeof(uint32_t) > kStreamListBytes, c->tpp,
                  c->unroll, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16, c->vel,
-                 c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st);
+                 c->frc, c->nbr, c->ncount, c->stride, c->cap, c->p.dt, c->part, c->st,
+                 FuseOut{c->pos_tmp, c->pos16_alt, c->xref, c->counts, nzero});
 }
 
 md_status grow_capacity(md_ctx c) {
@@ -291,10 +302,12 @@ ThermoArgs no_thermo() {
 }
 
 void launch_reductions(md_ctx c, hipStream_t s, int32_t step, const ThermoArgs& ta,
-                       int32_t energy = 1) {
-  if (c->nchunks) launch_reduce_chunks(s, c->nchunks, c->chunks, c->part, c->dmax, step, c->part2);
+                       int32_t energy = 1, int32_t drift_src = 0, int32_t next = 0) {
+  if (c->nchunks)
+    launch_reduce_chunks(s, c->nchunks, c->chunks, c->part, c->dmax, step, next, c->part2);
   launch_reduce(s, c->nrep, c->reps, c->part, c->dmax, c->nchunks ? c->part2 : nullptr, step,
-                energy, ta, c->kcall, c->lam, c->rebuild, c->obs, c->st);
+                energy, DriftArgs{drift_src, next, c->dpend}, ta, c->kcall, c->lam, c->rebuild,
+                c->obs, c->st);
 }
 
 // Split every replica's partial blocks [fb0, fb1) (and drift tiles) into
@@ -333,29 +346,45 @@ void launch_forces0(md_ctx c) {
 }
 
 
+// Directly launched NVE steps of a one-replica gather-path context can fuse
+// the next step's kick and drift into the force launch (md_params.split_kick).
+bool can_fuse(md_ctx c, int32_t thermo) {
+  return !thermo && c->nrep == 1 && !c->cells && !c->staged && c->p.split_kick == 0;
+}
+
 // One velocity-Verlet step on stream s (also used while capturing a graph).
 // energy: the step forms PE and W (the observables refreshed on it).
+// kick: launch this step's first half kick and drift (false when the
+// previous step's fused force launch applied them).  fuse: this step's force
+// launch applies the next step's kick and drift (force mode 2); the next
+// step is then enqueued with kick = false.
 md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t thermo, int32_t k,
-                       int32_t energy) {
+                       int32_t energy, bool kick = true, bool fuse = false) {
   // one replica: its histogram is read only inside a rebuild, so the kick
-  // clears it when its threads cover the cells (not in very dilute boxes)
-  // and the chain skips a launch
+  // (or the fused force launch before it) clears it when its threads cover
+  // the cells (not in very dilute boxes) and the chain skips a launch
   const bool zero_in_kick = c->nrep == 1 && (int64_t)c->ncells <= (int64_t)c->ntiles * kTile;
-  launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos, c->pos16,
-                    c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild, c->dmax,
-                    c->st, c->counts, zero_in_kick ? c->ncells : 0);
+  const int32_t nzero = zero_in_kick ? c->ncells : 0;
+  if (kick)
+    launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos,
+                      c->pos16, c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild,
+                      c->dmax, c->st, c->counts, nzero);
   run_chain(c, s, zero_in_kick);
   const bool timed = c->prof_every > 0 && (k + 1) % c->prof_every == 0;
   if (timed) {
     if (c->ev_pool.size() < c->ev_used + 2) return fail(c, MD_EHIP, "event pool exhausted");
     HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used], s));
   }
-  launch_forces(c, 1, s, energy);
+  launch_forces(c, fuse ? 2 : 1, s, energy, fuse ? nzero : 0);
   if (timed) {
     HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], s));
     c->ev_used += 2;
   }
-  launch_reductions(c, s, 1, ta, energy);
+  if (fuse) {
+    std::swap(c->pos, c->pos_tmp);
+    std::swap(c->pos16, c->pos16_alt);
+  }
+  launch_reductions(c, s, 1, ta, energy, kick ? 0 : 1, fuse ? 1 : 0);
   return MD_OK;
 }
 
@@ -392,10 +421,10 @@ void drop_graph(md_ctx c) {
 // A graph of K steps, captured once per launch configuration and replayed:
 // every argument is fixed, the step number lives in device counters.
 md_status ensure_graph(md_ctx c, const ThermoArgs& ta, int32_t thermo, int32_t K) {
-  const int64_t key[10] = {K, thermo, ta.ramp, ta.log_every, ta.nlog, (int64_t)(intptr_t)ta.log,
+  const int64_t key[11] = {K, thermo, ta.ramp, ta.log_every, ta.nlog, (int64_t)(intptr_t)ta.log,
                            (int64_t)(intptr_t)c->nbr, (int64_t)(intptr_t)c->nbr16,
-                           c->prof_every, c->prof_epoch};
-  if (c->gexec && std::equal(key, key + 10, c->gkey)) return MD_OK;
+                           c->prof_every, c->prof_epoch, (int64_t)(intptr_t)c->pos};
+  if (c->gexec && std::equal(key, key + 11, c->gkey)) return MD_OK;
   drop_graph(c);
   if (!c->cap_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   md_status rc = reserve_events(c, K);
@@ -416,7 +445,7 @@ md_status ensure_graph(md_ctx c, const ThermoArgs& ta, int32_t thermo, int32_t K
     c->gexec = nullptr;
     return fail(c, MD_EHIP, "graph instantiation failed");
   }
-  std::copy(key, key + 10, c->gkey);
+  std::copy(key, key + 11, c->gkey);
   return MD_OK;
 }
 
@@ -658,7 +687,10 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
     ALLOC(f, 3 * S);
     c->frc = f;
   }
-  if (c->mixed && !c->staged && !c->cells) ALLOC(c->pos16, S);
+  if (c->mixed && !c->staged && !c->cells) {
+    ALLOC(c->pos16, S);
+    ALLOC(c->pos16_alt, S);
+  }
   ALLOC(c->id, N);
   ALLOC(c->id_tmp, N);
   ALLOC(c->img, 3 * N);
@@ -680,7 +712,8 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
       (int32_t)((std::max((size_t)c->ntiles * 8, (size_t)c->nrt) + kRedChunk - 1) / kRedChunk) +
       nrep;
   ALLOC(c->chunks, (size_t)c->max_chunks);
-  ALLOC(c->part2, 4 * (size_t)c->max_chunks);
+  ALLOC(c->part2, (size_t)kPart2 * c->max_chunks);
+  ALLOC(c->dpend, (size_t)nrep);
   ALLOC(c->obs, (size_t)nrep);
   ALLOC(c->kcall, (size_t)nrep);
   ALLOC(c->lam, (size_t)nrep);
@@ -714,6 +747,7 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
             hipMemset(c->rebuild, 0, sizeof(int32_t) * nrep) == hipSuccess &&
             hipMemset(c->obs, 0, sizeof(md_obs) * nrep) == hipSuccess &&
             hipMemset(c->kcall, 0, sizeof(int64_t) * nrep) == hipSuccess &&
+            hipMemset(c->dpend, 0, sizeof(double) * nrep) == hipSuccess &&
             hipMemset(c->frc, 0, (c->mixed ? 4 : 8) * 3 * S) == hipSuccess;
   if (!ok) {
     md_destroy(c);
@@ -858,8 +892,12 @@ md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
     md_status rc = reserve_events(c, nsteps - k);
     if (rc) return rc;
   }
-  for (; k < nsteps; ++k) {
-    md_status rc = enqueue_step(c, s, ta, thermo, k, energy_step(ta, k, nsteps - 1));
+  // the last step of a call is never fused: the state it leaves (positions,
+  // velocities, forces) is complete
+  const bool fusable = can_fuse(c, thermo);
+  for (const int32_t k0 = k; k < nsteps; ++k) {
+    md_status rc = enqueue_step(c, s, ta, thermo, k, energy_step(ta, k, nsteps - 1),
+                                !(fusable && k > k0), fusable && k + 1 < nsteps);
     if (rc) return rc;
   }
   if (thermo) launch_apply_lambda(s, c->ntiles, c->tiles, c->stride, c->vel, c->lam, c->nrep);

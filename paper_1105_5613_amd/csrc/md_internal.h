@@ -203,12 +203,23 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
 // unroll: list slots gathered per pipelined chunk (1, 2, 4 or 8).
 // stream_list: read the list with non-temporal loads (lists larger than the
 // last-level cache; see kStreamListBytes).
+// Outputs of the force kernel's mode 2 (the next step's kick and drift
+// fused into an NVE step): the drifted positions (the other buffer of the
+// position pair), the list-build positions for the skin check, and the cell
+// histogram to clear (nzero cells; 0 = none).  Unused by modes 0 and 1.
+struct FuseOut {
+  double4* pos_out;
+  float4* pos16_out;
+  const double* xref;
+  int32_t* counts;
+  int32_t nzero;
+};
 void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t energy,
                   int32_t stream_list, int32_t tpp,
                   int32_t unroll, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                   const PairTab* tab, const double4* pos, const float4* pos16, double* vel,
                   void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
-                  int32_t cap, double dt, double* part, DevState* st);
+                  int32_t cap, double dt, double* part, DevState* st, const FuseOut& fo);
 // integrate.hip
 void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t ntiles,
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab,
@@ -227,25 +238,41 @@ struct ThermoArgs {
   int32_t pad;
 };
 // First level of the two-level reduction (large replicas): chunk c sums the
-// partial triples [b0, b1) and takes the maximum of the drift tile maxima
-// [t0, t1) into part2[4 c .. 4 c + 3].
+// partial triples [b0, b1), takes the maximum of the drift tile maxima
+// [t0, t1) and, with next = 1, of the fourth partials [b0, b1) (the next
+// step's drift measured by a fused force launch) into part2[kPart2 c + k],
+// k = 0..4 (pe, w, ke, tile maximum, next maximum).
 struct RedChunk {
   int32_t b0, b1, t0, t1;
 };
 constexpr int32_t kRedChunk = 1024;  // partial blocks per chunk
+constexpr int32_t kPart2 = 8;        // doubles per chunk result
 void launch_reduce_chunks(hipStream_t s, int32_t nchunks, const RedChunk* ch, const double* part,
-                          const double* dmax, int32_t step, double* part2);
+                          const double* dmax, int32_t step, int32_t next, double* part2);
+// Where a step's drift maximum comes from and what the reduction does with
+// the rebuild flag (one replica per context when next = 1):
+// src = 0: the kick/drift tile maxima in dmax; src = 1: pend[r], stored by
+// the previous step's reduction.  next = 0: the flag is cleared at the end
+// of the step (the next kick sets it again); next = 1: this step's force
+// launch drifted the positions of the next step (force mode 2), so the flag
+// is set from that drift (pend[r] keeps it for the next step's observables).
+struct DriftArgs {
+  int32_t src;
+  int32_t next;
+  double* pend;
+};
 // step = 0: observables of the current state only; step = 1: end of a step
-// part holds one (pe, w, ke) triple per force block; replica r owns blocks
-// [fb0, fb1).  dmax holds the kick/drift tile maxima of |x - x_ref|^2
-// (tiles [tile0, tile1) of replica r), read when step = 1.
-// With part2 != NULL the per-replica pass reads the chunk results
-// part2[4 c + k], c in [cb0, cb1), instead of part and dmax.  energy = 0:
-// the step formed no PE/W; pe, virial, P and E keep their last values.
+// part holds one (pe, w, ke, next drift) quadruple per force block; replica
+// r owns blocks [fb0, fb1).  dmax holds the kick/drift tile maxima of
+// |x - x_ref|^2 (tiles [tile0, tile1) of replica r), read when step = 1 and
+// drift.src = 0.  With part2 != NULL the per-replica pass reads the chunk
+// results part2[kPart2 c + k], c in [cb0, cb1), instead of part and dmax.
+// energy = 0: the step formed no PE/W; pe, virial, P and E keep their last
+// values.
 void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const double* part,
                    const double* dmax, const double* part2, int32_t step, int32_t energy,
-                   ThermoArgs ta, int64_t* kcall, double* lam, int32_t* rebuild, md_obs* obs,
-                   DevState* st);
+                   DriftArgs drift, ThermoArgs ta, int64_t* kcall, double* lam, int32_t* rebuild,
+                   md_obs* obs, DevState* st);
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* obs,
                         DevState* st);
 void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam);

@@ -330,6 +330,42 @@ def test_short_trajectory_matches_oracle(torch_cuda):
     assert ref["rebuilt"].sum() >= 2
 
 
+@pytest.mark.parametrize("precision,n,kw", [
+    (0, 4000, {}), (1, 4000, {}), (0, 32000, dict(tpp=4, unroll=2)),
+    (1, 32000, dict(tpp=1, unroll=8)), (0, 500, {}), (1, 864, dict(tpp=8, unroll=1)),
+])
+def test_fused_kick_matches_split(torch_cuda, precision, n, kw):
+    """NVE steps whose force launch also applies the next step's kick and
+    drift give bit for bit the trajectory of separate kick launches: state,
+    forces, every logged observable and the rebuild steps, across call
+    boundaries and with and without per-step energies."""
+    say(f"case fused kick vs split precision={precision} n={n} {kw}")
+    runs = []
+    for split in (0, 1):
+        sysm, s = make_system(torch_cuda, n, 5, precision, split_kick=split, **kw)
+        logs = [sysm.step(23, log_every=1)]
+        sysm.step(25)
+        logs.append(sysm.step(1, log_every=1))
+        logs.append(sysm.step(14, log_every=7))
+        sysm.step(2)
+        x, v, img = sysm.get_state()
+        F = sysm.get_forces()
+        runs.append((logs, x.cpu().numpy(), v.cpu().numpy(), img.cpu().numpy(),
+                     F.cpu().numpy(), sysm.observables()[0]))
+    (la, xa, va, ia, Fa, oa), (lb, xb, vb, ib, Fb, ob) = runs
+    assert np.array_equal(xa, xb)
+    assert np.array_equal(va, vb)
+    assert np.array_equal(ia, ib)
+    assert np.array_equal(Fa, Fb)
+    for a, b in zip(la, lb):
+        for key in a:
+            assert np.array_equal(a[key], b[key]), key
+    for key in oa:
+        assert oa[key] == ob[key], key
+    say(f"  rebuilds {oa['n_rebuild']} in {oa['step']} steps")
+    assert oa["n_rebuild"] >= 4 and oa["step"] == 65
+
+
 @pytest.mark.parametrize("path", ["gather", "staged"])
 def test_nve_drift_fp64_and_mixed(torch_cuda, path):
     """4,000 particles, dt = 0.005: steady-state drift below 1e-4 per particle."""
@@ -543,6 +579,28 @@ def test_graph_replays_match_direct(torch_cuda, precision):
     assert np.array_equal(x0, x1) and np.array_equal(v0, v1) and np.array_equal(i0, i1)
     for a, b in zip(l0, l1):
         for k in ("E", "T", "pe", "virial", "step", "n_rebuild"):
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_nve_graphs_between_fused_direct_steps(torch_cuda):
+    """NVE graph replays (separate kick launches) followed by directly launched
+    fused steps, an odd number of position-buffer swaps and a second call
+    that captures again: the same bits as plain direct launches."""
+    say("case NVE graphs and fused direct steps")
+    outs = []
+    for kw in (dict(graph_steps=0, split_kick=1), dict(graph_steps=10)):
+        sysm, s = make_system(torch_cuda, 4000, 5, **kw)
+        logs = [sysm.step(26, log_every=2)]
+        logs.append(sysm.step(20, log_every=5))
+        sysm.step(3)
+        x, v, img = sysm.get_state()
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), img.cpu().numpy(), logs,
+                     sysm.get_forces().cpu().numpy()))
+    (x0, v0, i0, l0, f0), (x1, v1, i1, l1, f1) = outs
+    assert np.array_equal(x0, x1) and np.array_equal(v0, v1) and np.array_equal(i0, i1)
+    assert np.array_equal(f0, f1)
+    for a, b in zip(l0, l1):
+        for k in a:
             assert np.array_equal(a[k], b[k]), k
 
 
