@@ -45,23 +45,26 @@ def log(*a):
 
 
 def force_bytes_per_particle(nbar: float, mixed: bool) -> float:
-    """Algorithmic HBM bytes per particle of one in-step force launch.
+    """Algorithmic HBM bytes per particle of one in-step force launch of an
+    NVE step, which also applies the next step's half kick and drift.
 
-    count (4) + list entries (4 nbar) + x_i (24) + species (4) + F write
-    (24 FP64 / 12 FP32) + v read and write of the fused second half kick (48).
-    Neighbour positions x_j are gathered from cache and not counted.
+    count (4) + list entries (4 nbar) + the home record (32: x_i and species
+    FP64; mixed: the 16-byte record and the 32-byte FP64 position) + v read
+    and write (48) + x_ref (24) + the drifted position written (32; mixed
+    also its 16-byte record).  The forces stay in registers.  Neighbour
+    positions x_j are gathered from cache and not counted.
     """
-    return 4 + 4 * nbar + 24 + 4 + (12 if mixed else 24) + 48
+    home = 16 + 32 if mixed else 32
+    out = 32 + 16 if mixed else 32
+    return 4 + 4 * nbar + home + 48 + 24 + out
 
 
 def step_bytes_per_particle(nbar: float, mixed: bool, rebuilds_per_step: float) -> float:
     """Algorithmic HBM bytes per particle-step of the whole step: the force
-    launch, the kick-drift (x, v, F, x_ref read; x, v written: 160 B FP64, 180
-    B mixed with the 16-byte record) and one rebuild (bin 28, sort keys 24,
+    launch (kick and drift included) and one rebuild (bin 28, sort keys 24,
     reorder 160, list write 4 nbar + 4) times the measured rebuilds per step."""
-    kick = 180.0 if mixed else 160.0
     rebuild = 28 + 24 + 160 + 4 * nbar + 4
-    return force_bytes_per_particle(nbar, mixed) + kick + rebuild * rebuilds_per_step
+    return force_bytes_per_particle(nbar, mixed) + rebuild * rebuilds_per_step
 
 
 def copy_gbs(torch) -> float:
@@ -272,7 +275,7 @@ def counters_summary(args):
            "copy_bytes": COPY_BYTES, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "copy_factor_fetch": copy_kib / cf, "copy_factor_write": copy_kib / cw,
            "forms": {}, "commands": args.commands}
-    for form, key in (("fp64", "k_force<false, 1"), ("mixed", "k_force<true, 1")):
+    for form, key in (("fp64", "k_force<false, 2"), ("mixed", "k_force<true, 2")):
         try:
             f, nf = mean_for(args.fetch_dir, "k_force", "FETCH_SIZE", key)
             w, nw = mean_for(args.write_dir, "k_force", "WRITE_SIZE", key)
@@ -439,7 +442,8 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),
-                "kernel": "k_force (pair forces + fused second half kick)",
+                "kernel": "k_force (pair forces, second half kick, next step's half kick, "
+                          "drift and skin check)",
                 "algorithmic_bytes_per_launch": round(n * bpp),
                 "force_ms_avg": round(head["force_ms_avg"], 5)}
         cgbs = copy_gbs(torch)
