@@ -113,9 +113,13 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
       mn = fmax(mn, part2[kPart2 * (size_t)b + 4]);
     }
   } else {
+#pragma unroll 4
     for (int32_t b = R.fb0 + threadIdx.x; b < R.fb1; b += kRedThreads) {
-      for (int k = 0; k < 3; ++k) neumaier(s[k], c[k], part[4 * (size_t)b + k]);
-      if (drift.next) mn = fmax(mn, part[4 * (size_t)b + 3]);
+      const double4 q = *reinterpret_cast<const double4*>(part + 4 * (size_t)b);
+      neumaier(s[0], c[0], q.x);
+      neumaier(s[1], c[1], q.y);
+      neumaier(s[2], c[2], q.z);
+      if (drift.next) mn = fmax(mn, q.w);
     }
     if (step && drift.src == 0)
       for (int32_t b = R.tile0 + threadIdx.x; b < R.tile1; b += kRedThreads)

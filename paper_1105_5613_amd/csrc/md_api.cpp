@@ -311,14 +311,15 @@ void launch_reductions(md_ctx c, hipStream_t s, int32_t step, const ThermoArgs& 
 }
 
 // Split every replica's partial blocks [fb0, fb1) (and drift tiles) into
-// chunks of about kRedChunk when some replica has more than 4 chunks' worth;
-// otherwise the per-replica pass reads the partials directly.  Host side
+// chunks of about kRedChunk when some replica has more than 16 chunks' worth;
+// otherwise the per-replica pass reads the partials directly (one launch
+// instead of two: up to 16 partials per thread of its block).  Host side
 // only: the caller uploads reps and chunks.
 void plan_chunks(md_ctx c) {
   int32_t most = 0;
   for (const RepDesc& d : c->reps_h) most = std::max(most, d.fb1 - d.fb0);
   c->chunks_h.clear();
-  if (most <= 4 * kRedChunk) {
+  if (most <= 16 * kRedChunk) {
     c->nchunks = 0;
     for (RepDesc& d : c->reps_h) d.cb0 = d.cb1 = 0;
     return;
