@@ -121,13 +121,15 @@ constexpr double kFar = 1.0e300;  // x of the idle lanes of a chunk: r^2 overflo
 
 // Append the hits of the lane's candidate for home particle hl of the group
 // (wave-uniform) at that particle's running count cnt.  Rows below rows_lds
-// go to the wave's LDS buffer ([row][home] layout) and reach the list later
-// as whole row segments; rows above it are stored straight into the home
-// particle's list row hrow (a wave-uniform pointer: one scalar base plus a
-// 32-bit lane offset per store).
+// go to the wave's LDS buffer ([home][row] layout: a wave-uniform base plus
+// the row, one full-rate address operation; rows_lds is odd, so the row
+// write-out, whose lanes read one row of consecutive homes, is free of bank
+// conflicts) and reach the list later as whole row segments; rows above it
+// are stored straight into the home particle's list row hrow (a wave-uniform
+// pointer: one scalar base plus a 32-bit lane offset per store).
 template <typename E>
 __device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_t hl,
-                                    uint32_t entry, int32_t cap, int32_t rows_lds, int32_t gn,
+                                    uint32_t entry, int32_t cap, int32_t rows_lds,
                                     uint32_t* buf, E* __restrict__ hrow) {
   if (mask) {
     const int32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -135,7 +137,7 @@ __device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_
     const int32_t k = cnt + rk;
     if (hit && k < cap) {
       if (k < rows_lds)
-        buf[k * gn + hl] = entry;
+        buf[hl * rows_lds + k] = entry;
       else
         *reinterpret_cast<E*>(reinterpret_cast<char*>(hrow) +
                               (uint32_t)k * (uint32_t)(kSlice * sizeof(E))) = (E)entry;
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   for (int32_t g0 = 0; g0 < nh; g0 += kCwGroup) {
     const int32_t gn = nh - g0 < kCwGroup ? nh - g0 : kCwGroup;
     const int32_t gbase = __builtin_amdgcn_readfirstlane(h0 + g0);  // wave-uniform
-    const int32_t rows_lds = BUF / gn;
+    const int32_t rows_lds = (BUF / gn - 1) | 1;  // odd, <= BUF / gn
     E* const grow = nbr + list_base(gbase, cap);
     int32_t cntv = 0;  // lane h: neighbours found so far for home gbase + h
     for (int32_t base = 0; base < ncand; base += 64) {
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
             const bool hit = SELF ? (k != i0 + u && ra[u] < tha[u]) : ra[u] < tha[u];
             const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
             int32_t cu = __builtin_amdgcn_readlane(cntv, h + u);
-            cu = cw_append(m, hit, cu, h + u, entry, cap, rows_lds, gn, buf,
+            cu = cw_append(m, hit, cu, h + u, entry, cap, rows_lds, buf,
                            home_row(grow, gbase, h + u, cap));
             cntv = write_lane(cntv, cu, h + u);
           }
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
         const bool hita = k != ia && ra < tha;
         const uint64_t ma = __builtin_amdgcn_ballot_w64(hita);
         int32_t ca = __builtin_amdgcn_readlane(cntv, h);
-        ca = cw_append(ma, hita, ca, h, entry, cap, rows_lds, gn, buf, home_row(grow, gbase, h, cap));
+        ca = cw_append(ma, hita, ca, h, entry, cap, rows_lds, buf, home_row(grow, gbase, h, cap));
         cntv = write_lane(cntv, ca, h);
       }
     }
@@ -392,7 +394,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
     const int32_t lr = lane / gn, lh = lane - lr * gn;
     if (lr < per)
       for (int32_t kk = lr; kk < rows; kk += per)
-        nbr[list_base(gbase + lh, cap) + (size_t)kk * kSlice] = (E)buf[kk * gn + lh];
+        nbr[list_base(gbase + lh, cap) + (size_t)kk * kSlice] = (E)buf[lh * rows_lds + kk];
     // the next group reuses the buffer
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
