@@ -126,12 +126,13 @@ def energy_drift(E, n: int, warmup: int):
 
 
 def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int,
-               path: int = 1, potential: int = 0, global_rc=None, dt: float = 0.005, T0=None):
+               path: int = 1, potential: int = 0, global_rc=None, dt: float = 0.005, T0=None,
+               graph_steps: int = 0):
     from paper_1105_5613_amd import System, make_params
     import initconf
     eps, sig, rc, mass = initconf.mixture_tables(global_rc=global_rc)
     p = make_params(eps, sig, rc, mass, skin=0.3, dt=dt, precision=precision, path=path,
-                    potential=potential)
+                    potential=potential, graph_steps=graph_steps)
     n = inputs["n"]
     sysm = System(p, [n], [inputs["L"]])
     sysm.set_state(inputs["x"], inputs["v"], inputs["type"])
@@ -293,7 +294,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--forms", default="fp64,mixed,large,batched,cells,soft")
+    ap.add_argument("--forms", default="fp64,mixed,small,large,batched,cells,soft")
     ap.add_argument("--profile-every", type=int, default=4,
                     help="bracket the force launch of every k-th timed step with hipEvents")
     ap.add_argument("--cpu-steps", type=int, default=80)
@@ -384,6 +385,20 @@ def main():
             "mean_list_length": round(rl["nbar"], 3), "rebuilds": rl["rebuilds"],
             "energy_drift_per_particle_per_1000_steps": rl["drift"],
             "tuned": rl["tuned"]}
+    if "small" in forms:
+        log(f"timing the 4000-particle box (FP64): {args.steps} steps, direct and in graphs")
+        small = initconf.fcc_system(4000, seed=1, temperature=2.0)
+        rd = run_single(torch, 0, small, args.steps, args.warmup, 0)
+        rg = run_single(torch, 0, small, args.steps, args.warmup, 0, graph_steps=100)
+        log(f"  small: direct {rd['rate']:.4e}, graphs {rg['rate']:.4e} particle-steps/s")
+        forms_out["small_fp64"] = {
+            "workload": "lj4000: 4,000-particle binary LJ mixture (FCC n=10, L=14.938, 5 cells "
+                        "per side), FP64, T=2.0 NVE, dt 0.005, skin 0.3; launch-bound",
+            "value_direct": round(rd["rate"], 1), "ms_per_step_direct": round(rd["ms_per_step"], 5),
+            "value_graphs_100": round(rg["rate"], 1),
+            "ms_per_step_graphs_100": round(rg["ms_per_step"], 5),
+            "rebuilds": rd["rebuilds"],
+            "energy_drift_per_particle_per_1000_steps": rd["drift"]}
     if "cells" in forms:
         log(f"timing the list-free cell path (FP64): {args.steps} steps")
         rcell = run_single(torch, 0, inputs, args.steps, args.warmup, args.profile_every, path=3)
