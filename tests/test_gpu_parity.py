@@ -479,11 +479,17 @@ def test_error_paths(torch_cuda):
 
 @pytest.mark.parametrize("path", ["gather", "staged"])
 def test_large_box_sampled(torch_cuda, path):
-    """1,048,576 particles: full lists bit-exact, sampled forces vs the oracle."""
+    """1,048,576 particles: full lists bit-exact, sampled forces vs the oracle;
+    energy, virial and kinetic totals through the one-level reduction and (FP64
+    gather with eight lanes per particle: 32,768 partial blocks) the
+    two-level one."""
     say(f"case 1M particles {path}")
     n = 1048576
     for precision in (0, 1):
-        sysm, s = make_system(torch_cuda, n, 2, precision=precision, **PATHS[path])
+        kw = dict(PATHS[path])
+        if path == "gather" and precision == 0:
+            kw.update(tpp=8, unroll=1)
+        sysm, s = make_system(torch_cuda, n, 2, precision=precision, **kw)
         p = oracle_params()
         sysm.step(20)
         x, v, img = sysm.get_state()
@@ -500,7 +506,6 @@ def test_large_box_sampled(torch_cuda, path):
         e = float(np.max(d / np.maximum(np.linalg.norm(Fo, axis=1), frms)))
         say(f"  precision {precision}: sampled force error {e:.3e}")
         assert e <= (1e-12 if precision == 0 else 1e-5)
-        # totals through the two-level reduction (more than 4,096 partial blocks)
         ob = sysm.observables()[0]
         _, pe_i, w_i = oracle.forces_cells(p, x, s["type"], s["L"])
         tol = 1e-12 if precision == 0 else 1e-6
