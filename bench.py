@@ -397,8 +397,7 @@ def main():
             "value_direct": round(rd["rate"], 1), "ms_per_step_direct": round(rd["ms_per_step"], 5),
             "value_graphs_100": round(rg["rate"], 1),
             "ms_per_step_graphs_100": round(rg["ms_per_step"], 5),
-            "rebuilds": rd["rebuilds"],
-            "energy_drift_per_particle_per_1000_steps": rd["drift"]}
+            "rebuilds": rd["rebuilds"]}
     if "cells" in forms:
         log(f"timing the list-free cell path (FP64): {args.steps} steps")
         rcell = run_single(torch, 0, inputs, args.steps, args.warmup, args.profile_every, path=3)
