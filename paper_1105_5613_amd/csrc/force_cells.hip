@@ -97,11 +97,13 @@ __device__ inline void pair_force(const PairLds<T>& P, const double4& p, int32_t
   a.w += fr * r2;
 }
 
+// Register budget for 6 waves per SIMD (80 VGPRs; 88-117 otherwise, 4-5
+// waves): the candidate loop is latency-bound, 1.36 -> 1.31 ms at 1M FP64.
 // NT = 2: the cutoff of (home species a, candidate species value s_b) is
 // rc2[0][a] + (rc2[1][a] - rc2[0][a]) s_b as one FMA (exact: the launch checks
 // the table, see fma_pair_form; the table is symmetric); NT = 4: a select.
 template <bool MIXED, int MODE, int NT>
-__global__ __launch_bounds__(kCellHomes) void k_force_cells(
+__global__ __launch_bounds__(kCellHomes) __attribute__((amdgpu_waves_per_eu(6))) void k_force_cells(
     const RowTile* __restrict__ rtiles, const RepDesc* __restrict__ reps,
     const PairTab* __restrict__ tab, const int32_t* __restrict__ cell_start,
     const double4* __restrict__ pos, double* __restrict__ vel, void* __restrict__ frc_,
