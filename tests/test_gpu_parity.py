@@ -450,6 +450,10 @@ def test_error_paths(torch_cuda):
     with pytest.raises(MDError) as ex:
         System(lib_params(), [500], [5.0])
     assert ex.value.code == -3
+    # unknown kick mode
+    with pytest.raises(MDError) as ex:
+        System(lib_params(split_kick=2), [500], [s["L"]])
+    assert ex.value.code == -1
     # bad species
     sysm = System(lib_params(), [500], [s["L"]])
     bad = s["type"].copy()
