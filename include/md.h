@@ -104,8 +104,10 @@ typedef struct {
   int32_t split_kick;    /* 0 = auto: in directly launched NVE steps of a one-replica
                             context on the gather path, the force launch of a step also
                             applies the next step's first half kick and drift (same
-                            arithmetic, one pass over the particles fewer per step);
-                            1 = always a separate kick/drift launch */
+                            arithmetic and results, one pass over the particles fewer per
+                            step; never on the last step of an md_step call, so the state
+                            it leaves is complete); 1 = always a separate kick/drift
+                            launch */
 } md_params;
 
 /* Per-replica observables after the last completed step. */
