@@ -5,7 +5,9 @@
 // forces; v += dt/2 F/m.  The second half kick runs inside the force kernel;
 // this file holds the first half kick and the drift, fused with the
 // displacement test |x - x_ref|^2 > (skin/2)^2 that schedules list rebuilds
-// and with the pending thermostat factor of the previous step.
+// and with the pending thermostat factor of the previous step.  (In NVE
+// steps of a one-replica context the force kernel's mode 2 applies the next
+// step's first half kick and drift itself, with the same arithmetic.)
 //
 // Canonical runs (fixed T, "BBMD scaling results"; the glass-section T ramp)
 // rescale v by lambda = sqrt(T_target / T_inst) after the second half kick,

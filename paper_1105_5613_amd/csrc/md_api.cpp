@@ -206,8 +206,9 @@ md_status sync_and_check(md_ctx c) {
   return MD_OK;
 }
 
-// zeroed: the kick of this step already cleared the cell histogram (one
-// replica, see launch_kick_drift's nzero)
+// zeroed: the kick of this step (or the fused force launch of the previous
+// step) already cleared the cell histogram (one replica, see
+// launch_kick_drift's nzero and FuseOut)
 void run_chain(md_ctx c, hipStream_t s, bool zeroed = false) {
   if (!zeroed) launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
   // several replicas rebuild at different steps: spread each one's blocks

@@ -199,7 +199,8 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   float4* pos16, int32_t spread);
 // force.hip
 // mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
-// half kick v += dt/2 F/m before KE, and PE/W only when energy != 0.
+// half kick v += dt/2 F/m before KE, and PE/W only when energy != 0;
+// mode 2: mode 1, then the next step's half kick and drift (FuseOut).
 // unroll: list slots gathered per pipelined chunk (1, 2, 4 or 8).
 // stream_list: read the list with non-temporal loads (lists larger than the
 // last-level cache; see kStreamListBytes).
