@@ -137,7 +137,8 @@ __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
   const RepDesc R = reps[t.rep];
   int32_t c = -1;
   if (active) {
-    double4 p = pos[i];
+    const double4 p0 = pos[i];
+    double4 p = p0;
     int32_t bad = 0;
     int32_t dx = wrap1(p.x, R.L, bad);
     int32_t dy = wrap1(p.y, R.L, bad);
@@ -149,7 +150,10 @@ __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
       img[o + 1] += dy;
       img[o + 2] += dz;
     }
-    pos[i] = p;
+    // most particles stay in the box: write back only a changed position
+    // (a tiny negative coordinate can wrap to L and then to 0 with no net
+    // image change)
+    if (bad || p.x != p0.x || p.y != p0.y || p.z != p0.z) pos[i] = p;
     int32_t qx = cell_coord(p.x, R.inv_cell, R.nc);
     int32_t qy = cell_coord(p.y, R.inv_cell, R.nc);
     int32_t qz = cell_coord(p.z, R.inv_cell, R.nc);
