@@ -1,0 +1,61 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic byte accounting of
+the force launch and the whole step, the drift estimator, the counter-traffic
+guard and the one-GPU guard."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_force_bytes_per_particle():
+    # count 4, entries 4 n, home record, v read+write 48, x_ref 24, drifted record(s)
+    n = 92.0
+    assert bench.force_bytes_per_particle(n, False) == pytest.approx(4 + 4 * n + 32 + 48 + 24 + 32)
+    assert bench.force_bytes_per_particle(n, True) == pytest.approx(
+        4 + 4 * n + (16 + 32) + 48 + 24 + (32 + 16))
+
+
+def test_step_bytes_add_the_rebuild_share():
+    n = 92.0
+    f = bench.force_bytes_per_particle(n, False)
+    rebuild = 28 + 24 + 160 + 4 * n + 4
+    assert bench.step_bytes_per_particle(n, False, 0.0) == pytest.approx(f)
+    assert bench.step_bytes_per_particle(n, False, 0.25) == pytest.approx(f + 0.25 * rebuild)
+
+
+def test_energy_drift_slope_and_short_window():
+    # E/N rising by 2e-5 per 1,000 steps plus a constant: the slope comes back
+    n, warmup = 1000, 50
+    k = np.arange(200)
+    step = warmup + bench.LOG_EVERY * (1 + k)
+    E = n * (3.0 + 2e-8 * step)
+    assert bench.energy_drift(E, n, warmup) == pytest.approx(2e-5, rel=1e-6)
+    # fewer than 900 steps after the 100-step burn-in: no figure
+    assert bench.energy_drift(E[:50], n, warmup) is None
+
+
+def test_counter_traffic_needs_the_current_kernel_source(tmp_path, monkeypatch):
+    d = {"force_src_sha256": bench.src_sha(), "copy_factor_fetch": 2.0,
+         "copy_factor_write": 1.0, "forms": {"fp64": {"fetch_kib": 10.0, "write_kib": 3.0}}}
+    p = tmp_path / "c.json"
+    p.write_text(json.dumps(d))
+    monkeypatch.setattr(bench, "COUNTERS_JSON", str(p))
+    assert bench.counters_traffic("fp64") == pytest.approx(10.0 * 1024 * 2.0 + 3.0 * 1024)
+    assert bench.counters_traffic("mixed") is None
+    d["force_src_sha256"] = "0" * 64
+    p.write_text(json.dumps(d))
+    assert bench.counters_traffic("fp64") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
