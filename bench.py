@@ -431,9 +431,14 @@ def main():
         bm = run_batched(torch, 1, systems, temps, args.batched_steps, 20, args.graph_steps)
         log(f"  batched fp64 {bf['rate']:.4e}, mixed {bm['rate']:.4e} particle-steps/s "
             f"({bf['particles']} particles)")
-        log(f"timing the same replicas one at a time: {args.serial_steps} steps each")
-        ser = run_one_at_a_time(torch, systems, temps, args.serial_steps)
-        log(f"  one at a time fp64 {ser['rate']:.4e} particle-steps/s")
+        ser = None
+        if args.serial_steps > 0:
+            log(f"timing the same replicas one at a time: {args.serial_steps} steps each")
+            ser = run_one_at_a_time(torch, systems, temps, args.serial_steps)
+            log(f"  one at a time fp64 {ser['rate']:.4e} particle-steps/s")
+
+        def vs_serial(rate):
+            return None if ser is None else round(rate / ser["rate"], 3)
         forms_out["batched"] = {
             "workload": f"replicas{args.replicas}: sizes log-uniform 1000..65536 "
                         f"({bf['particles']} particles), T0 in [0.4, 2.0], velocity rescale "
@@ -442,9 +447,9 @@ def main():
             "tuned_fp64": bf["tuned"], "tuned_mixed": bm["tuned"],
             "value_fp64": round(bf["rate"], 1), "value_mixed": round(bm["rate"], 1),
             "ms_per_step_fp64": round(bf["ms_per_step"], 5),
-            "one_at_a_time_fp64": round(ser["rate"], 1),
-            "speedup_batched_vs_one_at_a_time_fp64": round(bf["rate"] / ser["rate"], 3),
-            "speedup_batched_mixed_vs_one_at_a_time_fp64": round(bm["rate"] / ser["rate"], 3),
+            "one_at_a_time_fp64": None if ser is None else round(ser["rate"], 1),
+            "speedup_batched_vs_one_at_a_time_fp64": vs_serial(bf["rate"]),
+            "speedup_batched_mixed_vs_one_at_a_time_fp64": vs_serial(bm["rate"]),
             "max_rel_T_error": bf["max_rel_T_error"]}
     head = res.get("fp64") or res.get("mixed")
     head_mixed = "fp64" not in res
