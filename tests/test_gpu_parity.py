@@ -366,6 +366,32 @@ def test_fused_kick_matches_split(torch_cuda, precision, n, kw):
     assert oa["n_rebuild"] >= 4 and oa["step"] == 65
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_kick_matches_split_1m(torch_cuda, precision):
+    """The benchmark's box (1,048,576 particles, lists read with non-temporal
+    loads, two lanes per particle and four pipelined entries): 30 fused NVE
+    steps give the state, forces and observables of separate kick launches
+    bit for bit."""
+    say(f"case fused kick vs split at 1M precision={precision}")
+    outs = []
+    for split in (0, 1):
+        sysm, s = make_system(torch_cuda, 1048576, 2, precision, split_kick=split, tpp=2,
+                              unroll=4)
+        log = sysm.step(30, log_every=10)
+        x, v, img = sysm.get_state()
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), img.cpu().numpy(),
+                     sysm.get_forces().cpu().numpy(), log, sysm.observables()[0]))
+        sysm.close()
+    (xa, va, ia, fa, la, oa), (xb, vb, ib, fb, lb, ob) = outs
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(ia, ib)
+    assert np.array_equal(fa, fb)
+    for key in la:
+        assert np.array_equal(la[key], lb[key]), key
+    assert oa == ob
+    say(f"  rebuilds {oa['n_rebuild']} in {oa['step']} steps")
+    assert oa["n_rebuild"] >= 3
+
+
 @pytest.mark.parametrize("path", ["gather", "staged"])
 def test_nve_drift_fp64_and_mixed(torch_cuda, path):
     """4,000 particles, dt = 0.005: steady-state drift below 1e-4 per particle."""
