@@ -19,23 +19,33 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mdref.c")
-LIB = os.path.join(HERE, "libmdref.so")
+# MDREF_LIB selects another build of the same source (the sanitizer build)
+LIB = os.environ.get("MDREF_LIB") or os.path.join(HERE, "libmdref.so")
+SAN_LIB = os.path.join(HERE, "libmdref_san.so")
 MAXT = 4
 
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile libmdref.so with gcc (no FMA contraction, no fast-math)."""
-    if not force and os.path.exists(LIB):
-        return LIB
-    tmp = LIB + ".tmp"
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile libmdref.so with gcc (no FMA contraction, no fast-math).
+
+    sanitize=True builds libmdref_san.so instead, instrumented with
+    AddressSanitizer and UndefinedBehaviorSanitizer (every finding fatal);
+    a process loads it with the sanitizer runtimes preloaded.
+    """
+    out = SAN_LIB if sanitize else os.path.join(HERE, "libmdref.so")
+    if not force and os.path.exists(out):
+        return out
+    tmp = out + ".tmp"
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-fno-omit-frame-pointer", "-g"] if sanitize else []
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra", "-Werror",
-           "-Wno-unused-parameter", SRC, "-o", tmp, "-lm"]
+           "-Wno-unused-parameter", *san, SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 class Params(C.Structure):

@@ -362,12 +362,20 @@ int mdref_rdf(int64_t n, double L, const double* x, double rmax,
   long double* h = (long double*)calloc((size_t)nbins, sizeof(long double));
   if (!h) return -3;
   /* pair counts per bin: integers, so splitting the rows over threads and
-     adding the per-thread counts gives exactly the serial histogram */
+     adding the per-thread counts gives exactly the serial histogram.  A
+     thread whose count buffer cannot be allocated fails the whole call
+     (no pair may go uncounted). */
+  int failed = 0;
 #pragma omp parallel
   {
     int64_t* hl = (int64_t*)calloc((size_t)nbins, sizeof(int64_t));
+    if (!hl) {
+#pragma omp atomic write
+      failed = 1;
+    }
 #pragma omp for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; i < n; ++i) {
+      if (!hl) continue;
       for (int64_t j = i + 1; j < n; ++j) {
         double d[3];
         for (int q = 0; q < 3; ++q) d[q] = min_image(x[3 * i + q] - x[3 * j + q], L);
@@ -375,12 +383,19 @@ int mdref_rdf(int64_t n, double L, const double* x, double rmax,
         if (r < rmax) {
           int32_t b = (int32_t)(r / dr);
           if (b >= nbins) b = nbins - 1;
-          if (hl) hl[b] += 1;
+          hl[b] += 1;
         }
       }
+    }
+    if (hl) {
 #pragma omp critical
-    for (int32_t b = 0; b < nbins; ++b) h[b] += (long double)(hl ? hl[b] : 0);
-    free(hl);
+      for (int32_t b = 0; b < nbins; ++b) h[b] += (long double)hl[b];
+      free(hl);
+    }
+  }
+  if (failed) {
+    free(h);
+    return -3;
   }
   double V = L * L * L;
   const double pi = 3.14159265358979323846;
