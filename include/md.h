@@ -52,8 +52,11 @@ enum {
   MD_EINVAL = -1,     /* invalid argument (shape, range, non-finite input) */
   MD_ENOMEM = -2,     /* device allocation failed */
   MD_EBOX = -3,       /* box side L < 2 (max rc + skin) */
-  MD_EOVERFLOW = -4,  /* neighbour capacity exceeded; capacity has been grown,
-                         state must be set again (md_set_state) */
+  MD_EOVERFLOW = -4,  /* a neighbour row longer than the capacity.  md_build_cells
+                         and md_step grow the capacity and finish the call
+                         themselves (see there); returned only when growing
+                         cannot help: the staged path's 16383 LDS slots per row
+                         tile, or repeated growth within one call */
   MD_ENONFINITE = -5, /* a non-finite force or a particle that left the box by
                          more than one box length between rebuilds */
   MD_EHIP = -6,       /* a HIP runtime call failed */
@@ -161,41 +164,66 @@ md_status md_destroy(md_ctx ctx);
 const char* md_last_error(md_ctx ctx);
 
 /* Upload a state (DEVICE pointers, original id order): x, v [Ntot][3]
- * doubles, type [Ntot] int32 in [0, ntypes).  Positions must lie in
- * [-L, 2L) per coordinate.  Resets step and rebuild counters and image
- * counters; the next md_build_cells / md_forces / md_step rebuilds.
- * Invalid types or non-finite values are reported by this call (it
- * synchronises). */
+ * doubles, type [Ntot] int32 in [0, ntypes).  The particle record of the
+ * paper's data structure (position, velocity, species; "Grid-search
+ * method").  Positions must lie in [-L, 2L) per coordinate.  Resets step and
+ * rebuild counters and image counters; the next md_build_cells / md_forces /
+ * md_step rebuilds.  The arrays are copied; the caller keeps ownership.
+ * Errors: MD_EINVAL for a NULL array or a species outside [0, ntypes),
+ * MD_ENONFINITE for a non-finite value (this call synchronises). */
 md_status md_set_state(md_ctx ctx, const double* x, const double* v,
                        const int32_t* type);
 
 /* Download the state (DEVICE pointers, original id order, any may be NULL):
- * x [Ntot][3] positions as stored (wrapped at the last list build and
- * drifted since), v [Ntot][3], img [Ntot][3] int32 periodic image counters
- * (unwrapped position = x + img * L).  Synchronises. */
+ * x [Ntot][3] positions as stored (wrapped into the periodic box at the last
+ * list build, "Grid-search method", and drifted since), v [Ntot][3], img
+ * [Ntot][3] int32 periodic image counters (unwrapped position = x + img * L,
+ * the displacement behind the glass section's mean-squared displacement).
+ * The caller owns the buffers.  Synchronises; MD_ESTATE before a state is
+ * set; reports errors latched by earlier asynchronous calls. */
 md_status md_get_state(md_ctx ctx, double* x, double* v, int32_t* img);
 
-/* Wrap positions into [0, L), bin them into cells of side L/nc with
+/* The grid search ("Grid-search method", Fig. 1): wrap positions into
+ * [0, L), bin them into cubic cells of side L/nc >= max rc + skin with
  * nc = floor(L / (max rc + skin)) (nc < 3 -> one cell), order particles by
  * (cell, original id) and build the full neighbour list: j is listed for i
- * iff r_ij^2 < (rc_ab + skin)^2 over the 27-cell stencil.  Synchronises;
- * grows the capacity and rebuilds once if it overflowed. */
+ * iff r_ij^2 < (rc_ab + skin)^2 over the 27-cell stencil (the skin, the
+ * list and its reuse between builds are this library's, not the paper's).
+ * Synchronises; when a row overflows the capacity it grows the capacity and
+ * rebuilds once (MD_EOVERFLOW only when that cannot help). */
 md_status md_build_cells(md_ctx ctx);
 
 /* Evaluate forces, potential energy and virial on the current state
- * (building the list first when needed).  Asynchronous. */
+ * (building the list first when needed): the truncated pair potential of
+ * Eq. (1) or Eq. (2) in the shifted-force form Eq. (3) ("Interaction
+ * potential"), F_i = sum_j f(r_ij) (x_i - x_j) / r_ij over the pairs within
+ * rc_ab.  Forces stay in the context (md_get_forces).  Asynchronous;
+ * MD_ESTATE before a state is set. */
 md_status md_forces(md_ctx ctx);
 
-/* Copy the forces (DEVICE pointer, original id order, [Ntot][3]) as
- * doubles (MD_FP64) or floats (MD_MIXED).  Synchronises. */
+/* Copy the forces of the last md_forces / md_step (Eq. (3) summed over the
+ * pairs, "Interaction potential") to F (DEVICE pointer, caller-owned,
+ * original id order, [Ntot][3]) as doubles (MD_FP64) or floats
+ * (MD_MIXED).  Synchronises; MD_ESTATE before any force evaluation. */
 md_status md_get_forces(md_ctx ctx, void* F);
 
-/* Advance every replica by nsteps velocity-Verlet steps of length dt.
+/* Advance every replica by nsteps velocity-Verlet steps of length dt
+ * ("Parallel force calculation": half kick, drift, forces, half kick), with
+ * the cells and lists rebuilt whenever some particle of a replica moved more
+ * than skin/2 since its last build.
  * T0, T1: HOST [nrep] thermostat targets or NULL for NVE; the k-th step of
  * this call (k = 1..nsteps) rescales velocities to
- * T_target = T0 + (T1 - T0) min(k / ramp_steps, 1)  (ramp_steps <= 0: T0).
+ * T_target = T0 + (T1 - T0) min(k / ramp_steps, 1)  (ramp_steps <= 0: T0):
+ * the canonical runs of the scaling section and the linear cooling ramp of
+ * the glass section, by isokinetic rescaling (the paper names no mechanism).
  * log: HOST [nsteps / log_every][nrep] observables of every log_every-th
  * step, or NULL.  Synchronises at the end and reports latched errors.
+ * Capacity overflow: a rebuild whose longest row exceeds the neighbour
+ * capacity halts the steps queued after it; this call then grows the
+ * capacity, rebuilds that step's lists on its state and finishes the call,
+ * so the result is the one a context with enough capacity computes (bit for
+ * bit).  If growing cannot help, MD_EOVERFLOW is returned with the state of
+ * the interrupted step (drifted and re-sorted, forces not yet evaluated).
  * Forces, kinetic energy and T are formed every step; the pair sums behind
  * pe, virial, P and E only on the logged steps and the last step of the
  * call (inside a hipGraph chunk: also its last step, and every step when
@@ -205,7 +233,11 @@ md_status md_step(md_ctx ctx, int32_t nsteps, const double* T0,
                   const double* T1, int64_t ramp_steps, md_obs* log,
                   int32_t log_every);
 
-/* Observables of every replica (HOST [nrep]).  Synchronises. */
+/* Observables of every replica (HOST [nrep], caller-owned): kinetic and
+ * potential energy, virial, temperature, pressure and total energy (the
+ * per-rank quantities the paper reduces globally, "Parallel force
+ * calculation"; the potential energy of the glass section's caloric curve).
+ * Synchronises and reports errors latched by earlier asynchronous calls. */
 md_status md_observables(md_ctx ctx, md_obs* out);
 
 /* Parity hook, HOST pointers: cell_start [nc^3 + 1] (offsets local to the
@@ -270,6 +302,7 @@ md_status md_msd(md_ctx ctx, double* out);
  * otherwise all pairs are visited and the replica may hold at most 262144
  * particles.  rmax <= L/2, nbins <= 8192.  g HOST [nbins].  Synchronises. */
 md_status md_rdf(md_ctx ctx, int32_t rep, double rmax, int32_t nbins, double* g);
+
 
 /* Neighbour-list statistics of replica rep (rep = -1: all replicas) at the
  * last list build: mean and maximum entries per particle.  Synchronises. */

@@ -199,7 +199,16 @@ __global__ __launch_bounds__(256) void k_rdf_cells(int32_t c0, int32_t nc,
     if (s_h[b]) atomicAdd(&hist[b], (unsigned long long)s_h[b]);
 }
 
+__global__ void k_zero_u64(unsigned long long* __restrict__ a, int32_t n) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0ull;
+}
+
 }  // namespace
+
+void launch_zero_u64(hipStream_t s, unsigned long long* a, int32_t n) {
+  k_zero_u64<<<(n + 255) / 256, 256, 0, s>>>(a, n);
+}
 
 void launch_rdf_cells(hipStream_t s, int32_t c0, int32_t nc, const int32_t* cell_start,
                       const double4* pos, double L, double rmax, int32_t nbins,

@@ -75,6 +75,20 @@ __global__ void k_mark_rebuild(int32_t nrep, int32_t* rebuild, DevState* st) {
   if (r == 0) st->any_rebuild = 1;
 }
 
+// Capacity growth: row k of particle i moves from list_base(i, cap_old) +
+// k * kSlice to list_base(i, cap_new) + k * kSlice; rows past the old
+// capacity (truncated) are rebuilt afterwards.
+template <typename E>
+__global__ void k_relayout_list(int32_t ntot, const int32_t* __restrict__ ncount, int32_t cap_old,
+                                int32_t cap_new, const E* __restrict__ src, E* __restrict__ dst) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  const int32_t m = min(ncount[i], cap_old);
+  const E* a = src + list_base(i, cap_old);
+  E* b = dst + list_base(i, cap_new);
+  for (int32_t k = 0; k < m; ++k) b[(size_t)k * kSlice] = a[(size_t)k * kSlice];
+}
+
 __global__ void k_zero_counts(int32_t ncells, const int32_t* __restrict__ cell_rep,
                               const int32_t* __restrict__ rebuild, const DevState* st,
                               int32_t* __restrict__ counts) {
@@ -427,6 +441,16 @@ void launch_get_forces(hipStream_t s, int32_t ntot, int32_t stride, const void* 
   else
     k_get_forces<double><<<nblk(ntot, 256), 256, 0, s>>>(ntot, stride, (const double*)frc, id,
                                                         (double*)F);
+}
+
+void launch_relayout_list(hipStream_t s, int32_t ntot, const int32_t* ncount, int32_t cap_old,
+                          int32_t cap_new, int32_t elem, const void* src, void* dst) {
+  if (elem == 2)
+    k_relayout_list<uint16_t><<<nblk(ntot, 256), 256, 0, s>>>(
+        ntot, ncount, cap_old, cap_new, (const uint16_t*)src, (uint16_t*)dst);
+  else
+    k_relayout_list<uint32_t><<<nblk(ntot, 256), 256, 0, s>>>(
+        ntot, ncount, cap_old, cap_new, (const uint32_t*)src, (uint32_t*)dst);
 }
 
 void launch_mark_rebuild(hipStream_t s, int32_t nrep, int32_t* rebuild, DevState* st) {

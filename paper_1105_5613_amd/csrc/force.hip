@@ -6,11 +6,13 @@
 // FP64 form: everything in double; 1/r from an FP32 reciprocal-square-root
 // seed refined by two Newton-Raphson steps y <- y (3 - r^2 y^2) / 2, the
 // scheme the paper uses on BlueGene/P ("BlueGene specific optimizations").
-// Mixed form: neighbours are gathered as 16-byte FP32 records relative to
-// their build-time cell centre (make_rec16); the list entry carries the cell
-// offset d of the pair, so the displacement is (off_i - off_j) + d * side in
-// FP32 (a table lookup by the entry's code), with an absolute error of a few
-// 1e-7; one gather per entry instead of two; pair arithmetic and the
+// Mixed form: neighbours are gathered as 16-byte records holding their
+// offsets from the build-time cell centre in 32-bit fixed point (make_recq);
+// the list entry carries the cell offset d of the pair, so the displacement
+// is (off_i - off_j) + d * side, formed in FP64 from the exact integer
+// difference and a table of d * side by the entry's code (error ~1e-9 from
+// the fixed-point positions), with r^2 and the cut-off test in FP64; one
+// gather per entry instead of two; the pair arithmetic from r^2 on and the
 // per-particle force sum are FP32; per-particle energy/virial are widened to
 // FP64 for the reductions.
 //
@@ -146,13 +148,31 @@ template <bool MIXED, int MODE, int TPP, int U, bool EN, bool NTL>
 __global__ __launch_bounds__(kTile) void k_force(
     const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
     const PairTab* __restrict__ tab, const double4* __restrict__ pos,
-    const float4* __restrict__ pos16, double* __restrict__ vel, void* __restrict__ frc_,
+    const int4* __restrict__ pos16, double* __restrict__ vel, void* __restrict__ frc_,
     const uint32_t* __restrict__ nbr, const int32_t* __restrict__ ncount, int32_t stride,
     int32_t cap, double dt, double* __restrict__ part, DevState* st, FuseOut fo) {
   using T = typename std::conditional<MIXED, float, double>::type;
   __shared__ PairLds<T> P;
   __shared__ double s_mass[4], s_im[4];
-  __shared__ float4 s_doff[64];  // mixed: d * cell side for each entry code
+  __shared__ double4 s_doff[64];  // mixed: d * cell side for each entry code
+  __shared__ double s_rc2[16];    // mixed: cut-offs for the FP64 test
+  if (halted(st)) {
+    // a list build queued before this launch overflowed (see kHalt): the
+    // step is not taken; the later queued rebuild chains are switched off,
+    // and a fused launch hands the positions unchanged to the buffer the
+    // host swaps in
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->any_rebuild = 0;
+    if constexpr (MODE == 2) {
+      const int32_t hb = xcd_block(blockIdx.x, gridDim.x);
+      const Tile th = tiles[hb / TPP];
+      const int32_t ih = th.start + (hb % TPP) * (kTile / TPP) + threadIdx.x / TPP;
+      if (ih < th.end && threadIdx.x % TPP == 0) {
+        fo.pos_out[ih] = pos[ih];
+        if constexpr (MIXED) fo.pos16_out[ih] = pos16[ih];
+      }
+    }
+    return;
+  }
   load_pair<T>(P, tab);
   if (threadIdx.x < 4) {
     s_mass[threadIdx.x] = tab->mass[threadIdx.x];
@@ -171,11 +191,12 @@ __global__ __launch_bounds__(kTile) void k_force(
   const Tile t = tiles[tile_id];
   const RepDesc& Rp = reps[t.rep];
   if (MIXED && threadIdx.x < 64) {
-    const float sf = (float)Rp.cside;
+    const double sd = Rp.cside;
     const uint32_t c = threadIdx.x << kIdxBits;
-    s_doff[threadIdx.x] = make_float4((float)decode_shift(c, 26) * sf,
-                                      (float)decode_shift(c, 28) * sf,
-                                      (float)decode_shift(c, 30) * sf, 0.0f);
+    s_doff[threadIdx.x] = make_double4((double)decode_shift(c, 26) * sd,
+                                       (double)decode_shift(c, 28) * sd,
+                                       (double)decode_shift(c, 30) * sd, 0.0);
+    if (threadIdx.x < 16) s_rc2[threadIdx.x] = tab->rc2[threadIdx.x];
   }
   __syncthreads();
   const double L = Rp.L;
@@ -202,12 +223,13 @@ __global__ __launch_bounds__(kTile) void k_force(
       e[u] = k < n ? list_entry<NTL>(row + (size_t)k * kSlice) : self;
     }
     if constexpr (MIXED) {
-      // 16-byte cell-relative records (see make_rec16)
-      const float4 pi = pos16[i];
-      wbits = __float_as_uint(pi.w);
+      // 16-byte fixed-point cell-relative records (see make_recq)
+      const int4 pi = pos16[i];
+      const double qinv = Rp.qinv;
+      wbits = (uint32_t)pi.w;
       ti = (int32_t)(wbits >> 30);
       for (int32_t k0 = lane_p; k0 < n; k0 += U * TPP) {
-        float4 q[U];
+        int4 q[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) q[u] = pos16[e[u] & kIdxMask];
         uint32_t en[U];
@@ -218,13 +240,17 @@ __global__ __launch_bounds__(kTile) void k_force(
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          // (off_i - off_j) + d * side, d = c_i - c_j - s nc from the entry
-          const float4 dd = s_doff[e[u] >> kIdxBits];
-          const float ddx = (pi.x - q[u].x) + dd.x, ddy = (pi.y - q[u].y) + dd.y,
-                      ddz = (pi.z - q[u].z) + dd.z;
-          const int32_t ab = ti * 4 + (int32_t)(__float_as_uint(q[u].w) >> 30);
-          const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
+          // (off_i - off_j) + d * side, d = c_i - c_j - s nc from the entry:
+          // the integer difference is exact, the rest FP64
+          const double4 dd = s_doff[e[u] >> kIdxBits];
+          const double ex = __builtin_fma((double)(pi.x - q[u].x), qinv, dd.x),
+                       ey = __builtin_fma((double)(pi.y - q[u].y), qinv, dd.y),
+                       ez = __builtin_fma((double)(pi.z - q[u].z), qinv, dd.z);
+          const int32_t ab = ti * 4 + (int32_t)((uint32_t)q[u].w >> 30);
+          const double r2d = ex * ex + ey * ey + ez * ez;
+          if (k0 + u * TPP < n && r2d < s_rc2[ab]) {
+            const float r2 = (float)r2d;
+            const float ddx = (float)ex, ddy = (float)ey, ddz = (float)ez;
             const float rinv = __builtin_amdgcn_rsqf(r2);
             const float r2inv = rinv * rinv;
             const float sr2 = P.sig2[ab] * r2inv;
@@ -332,7 +358,7 @@ __global__ __launch_bounds__(kTile) void k_force(
       p.y += dt * v1;
       p.z += dt * v2;
       fo.pos_out[i] = p;
-      if constexpr (MIXED) fo.pos16_out[i] = make_rec16(p.x, p.y, p.z, wbits, Rp.cside);
+      if constexpr (MIXED) fo.pos16_out[i] = make_recq(p.x, p.y, p.z, wbits, Rp.cside, Rp.qs);
       const double e0 = p.x - fo.xref[i], e1 = p.y - fo.xref[stride + i],
                    e2 = p.z - fo.xref[2 * (size_t)stride + i];
       d2 = e0 * e0 + e1 * e1 + e2 * e2;
@@ -358,7 +384,7 @@ __global__ __launch_bounds__(kTile) void k_force(
 
 template <bool MIXED, int MODE, bool EN, bool NTL>
 void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const Tile* tiles,
-              const RepDesc* reps, const PairTab* tab, const double4* pos, const float4* pos16,
+              const RepDesc* reps, const PairTab* tab, const double4* pos, const int4* pos16,
               double* vel, void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
               int32_t cap, double dt, double* part, DevState* st, const FuseOut& fo) {
 #define KF(TPP, U)                                                                       \
@@ -388,7 +414,7 @@ void launch_t(hipStream_t s, int32_t tpp, int32_t unroll, int32_t ntiles, const 
 void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t energy,
                   int32_t stream_list, int32_t tpp,
                   int32_t unroll, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
-                  const PairTab* tab, const double4* pos, const float4* pos16, double* vel,
+                  const PairTab* tab, const double4* pos, const int4* pos16, double* vel,
                   void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
                   int32_t cap, double dt, double* part, DevState* st, const FuseOut& fo) {
 #define LT1(M, MO, EN, NTL)                                                                  \

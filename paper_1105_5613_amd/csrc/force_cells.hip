@@ -78,8 +78,10 @@ template <typename T>
 __device__ inline void pair_force(const PairLds<T>& P, const double4& p, int32_t ti, double qx,
                                   double qy, double qz, int32_t tj, Acc<T>& a) {
   const int32_t ab = ti * 4 + tj;
-  const T dx = (T)(p.x - qx), dy = (T)(p.y - qy), dz = (T)(p.z - qz);
-  const T r2 = dx * dx + dy * dy + dz * dz;
+  // displacement and r^2 in FP64 (the mixed form rounds them to FP32 after)
+  const double ex = p.x - qx, ey = p.y - qy, ez = p.z - qz;
+  const T dx = (T)ex, dy = (T)ey, dz = (T)ez;
+  const T r2 = (T)(ex * ex + ey * ey + ez * ez);
   T rinv;
   if constexpr (std::is_same<T, float>::value)
     rinv = __builtin_amdgcn_rsqf(r2);
@@ -113,6 +115,10 @@ __global__ __launch_bounds__(kCellHomes) __attribute__((amdgpu_waves_per_eu(6)))
   __shared__ PairLds<T> P;
   __shared__ double s_mass[4];
   __shared__ uint32_t s_hit[kHitBuf][kCellHomes];  // particle index | piece << 26
+  if (halted(st)) {  // an overflowed list build halts the queued steps (kHalt)
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->any_rebuild = 0;
+    return;
+  }
   const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
   const RowTile Tl = rtiles[tb];
   const RepDesc R = reps[Tl.rep];

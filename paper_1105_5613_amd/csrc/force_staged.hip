@@ -71,8 +71,12 @@ __global__ __launch_bounds__(kStageHomes* TPP) void k_force_staged(
   constexpr int BT = kStageHomes * TPP;
   __shared__ StageLayout S;
   __shared__ PairLds<T> P;
-  __shared__ double s_mass[4];
+  __shared__ double s_mass[4], s_rc2[16];
   extern __shared__ double dyn[];
+  if (halted(st)) {  // an overflowed list build halts the queued steps (kHalt)
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->any_rebuild = 0;
+    return;
+  }
   const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
   const RowTile Tl = rtiles[tb];
   const RepDesc R = reps[Tl.rep];
@@ -87,6 +91,7 @@ __global__ __launch_bounds__(kStageHomes* TPP) void k_force_staged(
     P.vc[k] = (T)tab->vc[k];
     P.fs[k] = (T)tab->fs[k];
     P.rc[k] = (T)tab->rc[k];
+    s_rc2[k] = tab->rc2[k];
   }
   if (threadIdx.x < 4) s_mass[threadIdx.x] = tab->mass[threadIdx.x];
   build_layout(S, Tl, R, cell_start);
@@ -141,9 +146,13 @@ __global__ __launch_bounds__(kStageHomes* TPP) void k_force_staged(
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int32_t ab = ti * 4 + (int32_t)(e[u] >> 14);
-        const T dx = (T)(p.x - qx[u]), dy = (T)(p.y - qy[u]), dz = (T)(p.z - qz[u]);
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
+        // displacement, r^2 and the cut-off test in FP64 (the mixed form
+        // rounds them to FP32 for the pair arithmetic)
+        const double ex = p.x - qx[u], ey = p.y - qy[u], ez = p.z - qz[u];
+        const double r2d = ex * ex + ey * ey + ez * ez;
+        if (k0 + u * TPP < n && r2d < s_rc2[ab]) {
+          const T dx = (T)ex, dy = (T)ey, dz = (T)ez;
+          const T r2 = (T)r2d;
           T rinv;
           if constexpr (MIXED)
             rinv = __builtin_amdgcn_rsqf(r2);

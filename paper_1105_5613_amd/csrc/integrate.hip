@@ -22,13 +22,14 @@ namespace {
 template <typename FT, bool THERMO>
 __global__ __launch_bounds__(kTile) void k_kick_drift(
     const Tile* __restrict__ tiles, const RepDesc* __restrict__ reps,
-    const PairTab* __restrict__ tab, double4* __restrict__ pos, float4* __restrict__ pos16,
+    const PairTab* __restrict__ tab, double4* __restrict__ pos, int4* __restrict__ pos16,
     double* __restrict__ vel, const FT* __restrict__ frc, const double* __restrict__ xref,
     int32_t stride, double dt,
     const double* __restrict__ lam, int32_t* __restrict__ rebuild,
     double* __restrict__ dmax, DevState* st, int32_t* __restrict__ counts, int32_t nzero) {
   __shared__ double s_im[4];
   __shared__ double s_red[kTile / 64];
+  if (halted(st)) return;  // an overflowed list build halts the queued steps
   if (threadIdx.x < 4) s_im[threadIdx.x] = tab->inv_mass[threadIdx.x];
   __syncthreads();
   const int32_t tb = xcd_block(blockIdx.x, gridDim.x);
@@ -56,7 +57,10 @@ __global__ __launch_bounds__(kTile) void k_kick_drift(
     p.y += dt * v1;
     p.z += dt * v2;
     pos[i] = p;
-    if (pos16) pos16[i] = make_rec16(p.x, p.y, p.z, __float_as_uint(pos16[i].w), reps[t.rep].cside);
+    if (pos16) {
+      const RepDesc& R = reps[t.rep];
+      pos16[i] = make_recq(p.x, p.y, p.z, (uint32_t)pos16[i].w, R.cside, R.qs);
+    }
     vel[i] = v0;
     vel[stride + i] = v1;
     vel[2 * (size_t)stride + i] = v2;
@@ -103,6 +107,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
                                                         int32_t* __restrict__ rebuild,
                                                         md_obs* __restrict__ obs, DevState* st) {
   __shared__ double red[5][kRedThreads];
+  if (halted(st)) return;  // the step was not taken (kHalt)
   const int32_t r = blockIdx.x;
   const RepDesc R = reps[r];
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
@@ -201,8 +206,10 @@ __global__ __launch_bounds__(kChunkThreads) void k_reduce_chunks(const RedChunk*
                                                                  const double* __restrict__ part,
                                                                  const double* __restrict__ dmax,
                                                                  int32_t step, int32_t next,
-                                                                 double* __restrict__ part2) {
+                                                                 double* __restrict__ part2,
+                                                                 const DevState* st) {
   __shared__ double red[5][kChunkThreads];
+  if (halted(st)) return;
   const RedChunk C = ch[blockIdx.x];
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
   double mn = 0.0;
@@ -248,7 +255,9 @@ __global__ void k_begin_call(int32_t nrep, int64_t* kcall, double* lam) {
 
 __global__ __launch_bounds__(kTile) void k_apply_lambda(const Tile* __restrict__ tiles,
                                                         int32_t stride, double* __restrict__ vel,
-                                                        const double* __restrict__ lam) {
+                                                        const double* __restrict__ lam,
+                                                        const DevState* st) {
+  if (halted(st)) return;  // the factor is applied when the host finishes the call
   const Tile t = tiles[xcd_block(blockIdx.x, gridDim.x)];
   const int32_t i = t.start + threadIdx.x;
   if (i >= t.end) return;
@@ -258,7 +267,8 @@ __global__ __launch_bounds__(kTile) void k_apply_lambda(const Tile* __restrict__
   vel[2 * (size_t)stride + i] *= l;
 }
 
-__global__ void k_reset_lambda(int32_t nrep, double* lam) {
+__global__ void k_reset_lambda(int32_t nrep, double* lam, const DevState* st) {
+  if (halted(st)) return;
   const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nrep) lam[r] = 1.0;
 }
@@ -269,7 +279,7 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t ntiles,
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab, double4* pos,
-                       float4* pos16, double* vel, const void* frc, const double* xref,
+                       int4* pos16, double* vel, const void* frc, const double* xref,
                        int32_t stride, double dt, const double* lam, int32_t* rebuild,
                        double* dmax, DevState* st, int32_t* counts, int32_t nzero) {
 #define KD(FT, TH)                                                                         \
@@ -293,8 +303,9 @@ void launch_reduce(hipStream_t s, int32_t nrep, const RepDesc* reps, const doubl
 }
 
 void launch_reduce_chunks(hipStream_t s, int32_t nchunks, const RedChunk* ch, const double* part,
-                          const double* dmax, int32_t step, int32_t next, double* part2) {
-  k_reduce_chunks<<<nchunks, kChunkThreads, 0, s>>>(ch, part, dmax, step, next, part2);
+                          const double* dmax, int32_t step, int32_t next, double* part2,
+                          const DevState* st) {
+  k_reduce_chunks<<<nchunks, kChunkThreads, 0, s>>>(ch, part, dmax, step, next, part2, st);
 }
 
 void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* obs,
@@ -307,9 +318,9 @@ void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam)
 }
 
 void launch_apply_lambda(hipStream_t s, int32_t ntiles, const Tile* tiles, int32_t stride,
-                         double* vel, double* lam, int32_t nrep) {
-  k_apply_lambda<<<ntiles, kTile, 0, s>>>(tiles, stride, vel, lam);
-  k_reset_lambda<<<nblk(nrep, 256), 256, 0, s>>>(nrep, lam);
+                         double* vel, double* lam, int32_t nrep, const DevState* st) {
+  k_apply_lambda<<<ntiles, kTile, 0, s>>>(tiles, stride, vel, lam, st);
+  k_reset_lambda<<<nblk(nrep, 256), 256, 0, s>>>(nrep, lam, st);
 }
 
 }  // namespace mdk

@@ -40,7 +40,7 @@ struct md_ctx_s {
   int32_t *cell_rep = nullptr, *counts = nullptr, *cell_start = nullptr, *bsum = nullptr;
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp_src = nullptr;
   double4 *pos = nullptr, *pos_tmp = nullptr;
-  float4* pos16 = nullptr;  // mixed form, gather path: cell-relative FP32 records
+  int4* pos16 = nullptr;  // mixed form, gather path: cell-relative FP32 records
   double *vel = nullptr, *vel_tmp = nullptr, *xref = nullptr;
   void* frc = nullptr;
   int32_t *id = nullptr, *id_tmp = nullptr, *img = nullptr;
@@ -53,7 +53,7 @@ struct md_ctx_s {
   // buffer of a pair, pos <-> pos_tmp (pos_tmp is scratch of the rebuild
   // chain otherwise) and pos16 <-> pos16_alt; dpend [nrep] holds the drift
   // maximum measured for the next step
-  float4* pos16_alt = nullptr;
+  int4* pos16_alt = nullptr;
   double* dpend = nullptr;
   // two-level reduction of the force partials (large replicas only)
   std::vector<RedChunk> chunks_h;
@@ -74,7 +74,7 @@ struct md_ctx_s {
   // captured K-step graphs (md_params.graph_steps)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int64_t gkey[11] = {0};
+  int64_t gkey[15] = {0};
   int32_t prof_epoch = 0;
   // force-kernel timing
   int32_t prof_every = 0;
@@ -196,6 +196,10 @@ md_status sync_and_check(md_ctx c) {
   if (st.err) {
     DevState z{};
     HIPCHECK(c, hipMemcpy(c->st, &z, sizeof(DevState), hipMemcpyHostToDevice));
+    if (st.err & kErrSlots)
+      return fail(c, MD_EOVERFLOW,
+                  "a staged row tile's neighbourhood exceeds 16383 LDS slots (use smaller "
+                  "tile_cells)");
     if (st.err & kErrOverflow)
       return fail(c, MD_EOVERFLOW, "neighbour list capacity exceeded");
     if (st.err & kErrType) return fail(c, MD_EINVAL, "species index out of range");
@@ -256,24 +260,44 @@ void launch_forces(md_ctx c, int32_t mode, hipStream_t s, int32_t energy = 1,
                  FuseOut{c->pos_tmp, c->pos16_alt, c->xref, c->counts, nzero});
 }
 
+void drop_graph(md_ctx c);
+
+// Grow the neighbour capacity after an overflowed build to the longest row it
+// found plus 16 (never below the old capacity).  The rows already built move
+// to the new layout (a replica that did not rebuild keeps its list bit for
+// bit); the overflowed rows are rebuilt by the caller.  A captured graph
+// holds the old list pointer and capacity and is dropped.
 md_status grow_capacity(md_ctx c) {
   std::vector<int32_t> cnt(c->ntot);
   HIPCHECK(c, hipMemcpy(cnt.data(), c->ncount, sizeof(int32_t) * c->ntot, hipMemcpyDeviceToHost));
   int32_t m = 0;
   for (int32_t v : cnt) m = std::max(m, v);
-  int32_t cap = ((m + 16 + 7) / 8) * 8;
+  if (m <= c->cap) return fail(c, MD_EOVERFLOW, "overflow flagged with every row within capacity");
+  const int32_t cap = std::max(c->cap, ((m + 16 + 7) / 8) * 8);
+  const int32_t elem = c->staged ? 2 : 4;
+  void* old = c->staged ? (void*)c->nbr16 : (void*)c->nbr;
   md_status rc;
+  void* fresh = nullptr;
   if (c->staged) {
-    dfree(c, c->nbr16);
-    c->nbr16 = nullptr;
-    rc = dalloc(c, &c->nbr16, list_elems(c->ntot, cap));
+    uint16_t* p = nullptr;
+    rc = dalloc(c, &p, list_elems(c->ntot, cap));
+    fresh = p;
   } else {
-    dfree(c, c->nbr);
-    c->nbr = nullptr;
-    rc = dalloc(c, &c->nbr, list_elems(c->ntot, cap));
+    uint32_t* p = nullptr;
+    rc = dalloc(c, &p, list_elems(c->ntot, cap));
+    fresh = p;
   }
   if (rc) return rc;
+  launch_relayout_list(c->stream, c->ntot, c->ncount, c->cap, cap, elem, old, fresh);
+  HIPCHECK(c, hipGetLastError());
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  dfree(c, old);
+  if (c->staged)
+    c->nbr16 = (uint16_t*)fresh;
+  else
+    c->nbr = (uint32_t*)fresh;
   c->cap = cap;
+  drop_graph(c);
   return MD_OK;
 }
 
@@ -291,6 +315,7 @@ md_status build_all(md_ctx c) {
       return MD_OK;
     }
     if (rc != MD_EOVERFLOW || attempt == 1) return rc;
+    if (c->err.find("LDS slots") != std::string::npos) return rc;  // not a capacity
     rc = grow_capacity(c);
     if (rc) return rc;
   }
@@ -305,7 +330,8 @@ ThermoArgs no_thermo() {
 void launch_reductions(md_ctx c, hipStream_t s, int32_t step, const ThermoArgs& ta,
                        int32_t energy = 1, int32_t drift_src = 0, int32_t next = 0) {
   if (c->nchunks)
-    launch_reduce_chunks(s, c->nchunks, c->chunks, c->part, c->dmax, step, next, c->part2);
+    launch_reduce_chunks(s, c->nchunks, c->chunks, c->part, c->dmax, step, next, c->part2,
+                         c->st);
   launch_reduce(s, c->nrep, c->reps, c->part, c->dmax, c->nchunks ? c->part2 : nullptr, step,
                 energy, DriftArgs{drift_src, next, c->dpend}, ta, c->kcall, c->lam, c->rebuild,
                 c->obs, c->st);
@@ -360,18 +386,23 @@ bool can_fuse(md_ctx c, int32_t thermo) {
 // previous step's fused force launch applied them).  fuse: this step's force
 // launch applies the next step's kick and drift (force mode 2); the next
 // step is then enqueued with kick = false.
+// resume: finish a step whose list build overflowed (kHalt): its kick and
+// drift are done and its histogram is stale, so the chain clears the counts
+// itself; drift_src (0: kick tile maxima, 1: the maximum the previous fused
+// force launch stored) is then the one of the interrupted step.
 md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t thermo, int32_t k,
-                       int32_t energy, bool kick = true, bool fuse = false) {
+                       int32_t energy, bool kick = true, bool fuse = false, bool resume = false,
+                       int32_t drift_src = -1) {
   // one replica: its histogram is read only inside a rebuild, so the kick
   // (or the fused force launch before it) clears it when its threads cover
   // the cells (not in very dilute boxes) and the chain skips a launch
   const bool zero_in_kick = c->nrep == 1 && (int64_t)c->ncells <= (int64_t)c->ntiles * kTile;
   const int32_t nzero = zero_in_kick ? c->ncells : 0;
-  if (kick)
+  if (kick && !resume)
     launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos,
                       c->pos16, c->vel, c->frc, c->xref, c->stride, c->p.dt, c->lam, c->rebuild,
                       c->dmax, c->st, c->counts, nzero);
-  run_chain(c, s, zero_in_kick);
+  run_chain(c, s, zero_in_kick && !resume);
   const bool timed = c->prof_every > 0 && (k + 1) % c->prof_every == 0;
   if (timed) {
     if (c->ev_pool.size() < c->ev_used + 2) return fail(c, MD_EHIP, "event pool exhausted");
@@ -386,7 +417,8 @@ md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t th
     std::swap(c->pos, c->pos_tmp);
     std::swap(c->pos16, c->pos16_alt);
   }
-  launch_reductions(c, s, 1, ta, energy, kick ? 0 : 1, fuse ? 1 : 0);
+  launch_reductions(c, s, 1, ta, energy, drift_src >= 0 ? drift_src : (kick ? 0 : 1),
+                    fuse ? 1 : 0);
   return MD_OK;
 }
 
@@ -402,6 +434,30 @@ int32_t energy_step_graph(const ThermoArgs& ta, int32_t k, int32_t K) {
   if (k == K - 1) return 1;
   if (ta.log_every <= 0) return 0;
   return K % ta.log_every != 0 || (k + 1) % ta.log_every == 0;
+}
+
+md_status reserve_events(md_ctx c, int32_t nsteps);
+
+// Directly launched steps [k0, nsteps) of an md_step call whose steps
+// [0, kg) ran inside graph replays.  A step launched here after another one
+// of this loop had its kick and drift applied by that step's force launch
+// when the call can fuse.  resume: step k0 was interrupted by an overflowed
+// list build after its kick and drift; its drift maximum is where that kick
+// left it (the previous force launch's partials for a fused direct step, the
+// kick's tile maxima otherwise).
+md_status enqueue_direct(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t thermo,
+                         int32_t kg, int32_t k0, int32_t nsteps, bool fusable, bool resume) {
+  md_status rc = reserve_events(c, nsteps - k0);
+  if (rc) return rc;
+  for (int32_t k = k0; k < nsteps; ++k) {
+    const bool res = resume && k == k0;
+    const bool kick = !res && !(fusable && k > k0);
+    const int32_t src = res ? (fusable && k > kg ? 1 : 0) : -1;
+    rc = enqueue_step(c, s, ta, thermo, k, energy_step(ta, k, nsteps - 1), kick,
+                      fusable && k + 1 < nsteps, res, src);
+    if (rc) return rc;
+  }
+  return MD_OK;
 }
 
 md_status reserve_events(md_ctx c, int32_t nsteps) {
@@ -423,10 +479,11 @@ void drop_graph(md_ctx c) {
 // A graph of K steps, captured once per launch configuration and replayed:
 // every argument is fixed, the step number lives in device counters.
 md_status ensure_graph(md_ctx c, const ThermoArgs& ta, int32_t thermo, int32_t K) {
-  const int64_t key[11] = {K, thermo, ta.ramp, ta.log_every, ta.nlog, (int64_t)(intptr_t)ta.log,
+  const int64_t key[15] = {K, thermo, ta.ramp, ta.log_every, ta.nlog, (int64_t)(intptr_t)ta.log,
                            (int64_t)(intptr_t)c->nbr, (int64_t)(intptr_t)c->nbr16,
-                           c->prof_every, c->prof_epoch, (int64_t)(intptr_t)c->pos};
-  if (c->gexec && std::equal(key, key + 11, c->gkey)) return MD_OK;
+                           c->prof_every, c->prof_epoch, (int64_t)(intptr_t)c->pos,
+                           c->cap, c->lcap_f, c->tpp, c->unroll};
+  if (c->gexec && std::equal(key, key + 15, c->gkey)) return MD_OK;
   drop_graph(c);
   if (!c->cap_stream) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   md_status rc = reserve_events(c, K);
@@ -447,7 +504,7 @@ md_status ensure_graph(md_ctx c, const ThermoArgs& ta, int32_t thermo, int32_t K
     c->gexec = nullptr;
     return fail(c, MD_EHIP, "graph instantiation failed");
   }
-  std::copy(key, key + 11, c->gkey);
+  std::copy(key, key + 15, c->gkey);
   return MD_OK;
 }
 
@@ -508,6 +565,11 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
     d.dof = 3.0 * (double)n[r] - 3.0;
     d.volume = L[r] * L[r] * L[r];
     d.cside = L[r] / nc;
+    // mixed records: the largest power of two scale s.t. half a cell side
+    // plus the skin plus one unit of drift stays below 2^30 fixed-point units
+    d.qs = 1.0;
+    while ((0.5 * d.cside + p->skin + 1.0) * (2.0 * d.qs) <= 1073741824.0) d.qs *= 2.0;
+    d.qinv = 1.0 / d.qs;
     d.off = off;
     d.n = (int32_t)n[r];
     d.coff = coff;
@@ -890,29 +952,46 @@ md_status md_step(md_ctx c, int32_t nsteps, const double* T0, const double* T1,
     if (rc) return rc;
     for (; k + K <= nsteps; k += K) HIPCHECK(c, hipGraphLaunch(c->gexec, s));
   }
-  {
-    md_status rc = reserve_events(c, nsteps - k);
-    if (rc) return rc;
-  }
+  const int32_t kg = k;  // steps [0, kg) ran inside graph replays
   // the last step of a call is never fused: the state it leaves (positions,
   // velocities, forces) is complete
   const bool fusable = can_fuse(c, thermo);
-  for (const int32_t k0 = k; k < nsteps; ++k) {
-    md_status rc = enqueue_step(c, s, ta, thermo, k, energy_step(ta, k, nsteps - 1),
-                                !(fusable && k > k0), fusable && k + 1 < nsteps);
-    if (rc) return rc;
-  }
-  if (thermo) launch_apply_lambda(s, c->ntiles, c->tiles, c->stride, c->vel, c->lam, c->nrep);
+  md_status rc = enqueue_direct(c, s, ta, thermo, kg, kg, nsteps, fusable, false);
+  if (rc) return rc;
+  if (thermo) launch_apply_lambda(s, c->ntiles, c->tiles, c->stride, c->vel, c->lam, c->nrep, c->st);
   HIPCHECK(c, hipGetLastError());
-  md_status rc = sync_and_check(c);
+  // a list build that overflowed halted the queued steps (kHalt): grow the
+  // capacity, rebuild the interrupted step's lists on its state and finish
+  // the call from there -- the trajectory of a context with enough capacity
+  for (int attempt = 0;; ++attempt) {
+    HIPCHECK(c, hipStreamSynchronize(s));
+    DevState st{};
+    HIPCHECK(c, hipMemcpy(&st, c->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    if (!(st.err & kErrOverflow) || (st.err & ~kErrOverflow) || attempt == 8) break;
+    int64_t done = 0;
+    HIPCHECK(c, hipMemcpy(&done, c->kcall, sizeof(int64_t), hipMemcpyDeviceToHost));
+    rc = grow_capacity(c);
+    if (rc) {
+      c->built = false;
+      c->forces_valid = false;
+      return rc;
+    }
+    st.err = 0;
+    st.any_rebuild = 1;  // the interrupted step's rebuild flags are still set
+    HIPCHECK(c, hipMemcpy(c->st, &st, sizeof(DevState), hipMemcpyHostToDevice));
+    rc = enqueue_direct(c, s, ta, thermo, kg, (int32_t)done, nsteps, fusable, true);
+    if (rc) return rc;
+    if (thermo)
+      launch_apply_lambda(s, c->ntiles, c->tiles, c->stride, c->vel, c->lam, c->nrep, c->st);
+    HIPCHECK(c, hipGetLastError());
+  }
+  rc = sync_and_check(c);
   if (rc == MD_EOVERFLOW) {
-    md_status g = grow_capacity(c);
+    // not recoverable by growing the list (staged tile slots, or repeated
+    // growth): the state is the interrupted step's
     c->built = false;
     c->forces_valid = false;
-    if (g) return g;
-    return fail(c, MD_EOVERFLOW,
-                "neighbour list capacity exceeded during md_step; capacity grown, set the "
-                "state again");
+    return rc;
   }
   if (rc) return rc;
   if (log && nlog > 0)
@@ -1131,13 +1210,14 @@ md_status md_msd(md_ctx c, double* out) {
   return MD_OK;
 }
 
-md_status md_rdf(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g) {
-  if (!c) return MD_EINVAL;
-  if (rep < 0 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
-  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+namespace {
+// g(r) of replica rep into g (HOST [nbins]) from the pair histogram hist
+// (DEVICE, >= nbins counters, cleared here).  The counts are copied into g's
+// own storage (8 bytes each) and normalised in place.  may_build: build the
+// cells first when the cell sweep needs them.
+md_status rdf_with(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g,
+                   unsigned long long* hist, bool may_build) {
   const RepDesc& d = c->reps_h[rep];
-  if (!g || nbins < 1 || nbins > 8192 || !(rmax > 0.0) || rmax > 0.5 * d.L)
-    return fail(c, MD_EINVAL, "need g, 1 <= nbins <= 8192 and 0 < rmax <= L/2");
   // the cell sweep covers every pair closer than the cell side minus the
   // skin while the skin rule holds; otherwise all pairs are visited
   const bool by_cells = d.nc >= 3 && rmax <= d.L / d.nc - c->p.skin;
@@ -1146,34 +1226,51 @@ md_status md_rdf(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g) {
                 "md_rdf: rmax above the cell side minus the skin needs a replica of at most "
                 "262144 particles");
   if (by_cells && !c->built) {
+    if (!may_build) return fail(c, MD_ESTATE, "md_rdf: cells not built");
     md_status b = build_all(c);
     if (b) return b;
   }
-  unsigned long long* hist = nullptr;
-  md_status rc = dalloc(c, &hist, (size_t)nbins);
+  launch_zero_u64(c->stream, hist, nbins);
+  if (by_cells)
+    launch_rdf_cells(c->stream, d.coff, d.nc, c->cell_start, c->pos, d.L, rmax, nbins, hist);
+  else
+    launch_rdf(c->stream, c->pos, d.off, d.n, d.L, rmax, nbins, hist);
+  HIPCHECK(c, hipGetLastError());
+  md_status rc = sync_and_check(c);
   if (rc) return rc;
-  hipError_t e = hipMemsetAsync(hist, 0, sizeof(unsigned long long) * nbins, c->stream);
-  if (e == hipSuccess) {
-    if (by_cells)
-      launch_rdf_cells(c->stream, d.coff, d.nc, c->cell_start, c->pos, d.L, rmax, nbins, hist);
-    else
-      launch_rdf(c->stream, c->pos, d.off, d.n, d.L, rmax, nbins, hist);
-  }
-  std::vector<unsigned long long> h(nbins);
-  rc = sync_and_check(c);
-  if (!rc && e == hipSuccess)
-    e = hipMemcpy(h.data(), hist, sizeof(unsigned long long) * nbins, hipMemcpyDeviceToHost);
-  dfree(c, hist);
-  if (rc) return rc;
-  if (e != hipSuccess) return fail(c, MD_EHIP, "md_rdf: HIP call failed");
+  HIPCHECK(c, hipMemcpy(g, hist, sizeof(unsigned long long) * nbins, hipMemcpyDeviceToHost));
   const double dr = rmax / nbins, V = d.L * d.L * d.L, n = (double)d.n;
   const double pi = 3.14159265358979323846;
   for (int32_t b = 0; b < nbins; ++b) {
+    unsigned long long h;
+    std::memcpy(&h, &g[b], sizeof h);
     const double r0 = b * dr, r1 = (b + 1) * dr;
     const double shell = 4.0 / 3.0 * pi * (r1 * r1 * r1 - r0 * r0 * r0);
-    g[b] = 2.0 * V * (double)h[b] / (n * n * shell);
+    g[b] = 2.0 * V * (double)h / (n * n * shell);
   }
   return MD_OK;
+}
+
+md_status rdf_args(md_ctx c, int32_t rep, double rmax, int32_t nbins, const double* g) {
+  if (rep < 0 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
+  if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
+  const RepDesc& d = c->reps_h[rep];
+  if (!g || nbins < 1 || nbins > 8192 || !(rmax > 0.0) || rmax > 0.5 * d.L)
+    return fail(c, MD_EINVAL, "need g, 1 <= nbins <= 8192 and 0 < rmax <= L/2");
+  return MD_OK;
+}
+}  // namespace
+
+md_status md_rdf(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g) {
+  if (!c) return MD_EINVAL;
+  md_status rc = rdf_args(c, rep, rmax, nbins, g);
+  if (rc) return rc;
+  unsigned long long* hist = nullptr;
+  rc = dalloc(c, &hist, (size_t)nbins);
+  if (rc) return rc;
+  rc = rdf_with(c, rep, rmax, nbins, g, hist, true);
+  dfree(c, hist);
+  return rc;
 }
 
 md_status md_list_stats(md_ctx c, int32_t rep, double* mean, int32_t* max) {

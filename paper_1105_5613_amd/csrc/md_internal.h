@@ -31,10 +31,19 @@ constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
 // error word bits (latched on the device, read at synchronising calls)
 enum : int32_t {
   kErrNonFinite = 1,
-  kErrOverflow = 2,
+  kErrOverflow = 2,   // a neighbour row longer than the list capacity
   kErrStray = 4,
   kErrType = 8,
+  kErrSlots = 16,     // staged path: a tile neighbourhood beyond the 14-bit slots
 };
+// A list build that overflowed halts the rest of the queued step sequence:
+// the force, reduction, kick and rescale kernels read this mask first and
+// return at once, and the first halted force launch clears any_rebuild so
+// the rebuild chains of the later queued steps exit too.  The state is left
+// as the overflowing build made it (drifted, wrapped and re-sorted positions,
+// half-kicked velocities); the host grows the capacity and finishes the
+// interrupted step from there.
+constexpr int32_t kHalt = kErrOverflow | kErrSlots;
 
 // Neighbour lists are stored as sliced ELL: slice s holds particles
 // [256 s, 256 s + 256) and stores its cap rows one after another, row k
@@ -68,26 +77,40 @@ struct RepDesc {       // per-replica geometry, device resident
   int32_t fb0, fb1;    // force-kernel partial blocks [fb0, fb1) of this replica
   int32_t cb0, cb1;    // reduction chunks [cb0, cb1) (two-level reduction only)
   double cside;        // cell side L / nc
+  double qs, qinv;     // mixed records: fixed-point scale 2^s and 2^-s (make_recq)
 };
 
-// Mixed form gather record of a particle (16 B): FP32 offsets from the centre
+// Mixed form gather record of a particle (16 B): the offsets from the centre
 // of the cell it was binned into at the last list build, (c + 1/2) * cside
-// formed in FP64, and a word holding the cell coordinates (10 bits each,
-// for the record updates of the drift) and the species (bits 30-31).  With
-// s the periodic image of a listed pair, x_i - (x_j + s L) equals
+// formed in FP64, as 32-bit fixed-point integers in units of 2^-s (qinv; s
+// per replica so that every offset a record can hold -- half a cell side
+// plus the skin and one step's drift -- stays below 2^30 units: 2^-28 =
+// 3.7e-9 for the LJ workloads), and a word holding the cell coordinates (10
+// bits each, for the record updates of the drift) and the species (bits
+// 30-31).  With s the periodic image of a listed pair, x_i - (x_j + s L)
+// equals
 //   (off_i - off_j) + (c_i - c_j - s nc) * cside
 // exactly; mixed lists carry d = c_i - c_j - s nc in {-1, 0, 1}^3, and the
-// force kernel forms the displacement in FP32 from the records and d * cside
-// rounded to FP32.
+// force kernel forms the displacement in FP64 from the exact integer offset
+// difference and d * cside, then does the pair arithmetic in FP32.  (FP32
+// offsets rounded the displacement to 6e-8 of the cell side, which the pair
+// force's stiffness turned into most of the mixed form's force error.)
 __device__ inline uint32_t pack_cell(int32_t cx, int32_t cy, int32_t cz, int32_t t) {
   return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20) | ((uint32_t)t << 30);
 }
-__device__ inline float4 make_rec16(double x, double y, double z, uint32_t w, double cside) {
+__device__ inline int32_t to_fixed(double u) {
+  // |u| beyond 2^30 units only in a step whose skin check rebuilds the record
+  // before any force launch reads it; clamped to stay defined
+  u = u > 1073741824.0 ? 1073741824.0 : (u < -1073741824.0 ? -1073741824.0 : u);
+  return __double2int_rn(u);
+}
+__device__ inline int4 make_recq(double x, double y, double z, uint32_t w, double cside,
+                                 double qs) {
   const int32_t cx = (int32_t)(w & 1023u), cy = (int32_t)((w >> 10) & 1023u),
                 cz = (int32_t)((w >> 20) & 1023u);
-  return make_float4((float)(x - ((double)cx + 0.5) * cside),
-                     (float)(y - ((double)cy + 0.5) * cside),
-                     (float)(z - ((double)cz + 0.5) * cside), __uint_as_float(w));
+  return make_int4(to_fixed((x - ((double)cx + 0.5) * cside) * qs),
+                   to_fixed((y - ((double)cy + 0.5) * cside) * qs),
+                   to_fixed((z - ((double)cz + 0.5) * cside) * qs), (int32_t)w);
 }
 
 // Per species pair ab = a * 4 + b.  The pair function Eq. (3) is written as
@@ -147,6 +170,7 @@ struct DevState {      // context scalars the kernels update
   int32_t any_rebuild;
   int32_t pad[2];
 };
+__device__ inline bool halted(const DevState* st) { return (st->err & kHalt) != 0; }
 
 // ---- launchers (each file owns its kernels) ----------------------------------
 // cells.hip
@@ -158,6 +182,11 @@ void launch_get_state(hipStream_t s, int32_t ntot, int32_t stride, const double4
 void launch_get_forces(hipStream_t s, int32_t ntot, int32_t stride, const void* frc,
                        int32_t mixed, const int32_t* id, void* F);
 void launch_mark_rebuild(hipStream_t s, int32_t nrep, int32_t* rebuild, DevState* st);
+// Copy every particle's first min(ncount, cap_old) list entries from the
+// sliced-ELL layout of capacity cap_old to that of capacity cap_new (elem 2
+// or 4 bytes), when the capacity grows.
+void launch_relayout_list(hipStream_t s, int32_t ntot, const int32_t* ncount, int32_t cap_old,
+                          int32_t cap_new, int32_t elem, const void* src, void* dst);
 void launch_zero_counts(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* rebuild, const DevState* st, int32_t* counts);
 void launch_bin(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
@@ -196,7 +225,7 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   double4* pos, double* vel, int32_t* id, double* xref,
                   uint32_t* nbr, int32_t* ncount, DevState* st, int32_t ncells,
                   const int32_t* cell_rep, int32_t any_single, int32_t any_multi,
-                  float4* pos16, int32_t spread);
+                  int4* pos16, int32_t spread);
 // force.hip
 // mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
 // half kick v += dt/2 F/m before KE, and PE/W only when energy != 0;
@@ -210,7 +239,7 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
 // histogram to clear (nzero cells; 0 = none).  Unused by modes 0 and 1.
 struct FuseOut {
   double4* pos_out;
-  float4* pos16_out;
+  int4* pos16_out;
   const double* xref;
   int32_t* counts;
   int32_t nzero;
@@ -218,13 +247,13 @@ struct FuseOut {
 void launch_force(hipStream_t s, int32_t mixed, int32_t mode, int32_t energy,
                   int32_t stream_list, int32_t tpp,
                   int32_t unroll, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
-                  const PairTab* tab, const double4* pos, const float4* pos16, double* vel,
+                  const PairTab* tab, const double4* pos, const int4* pos16, double* vel,
                   void* frc, const uint32_t* nbr, const int32_t* ncount, int32_t stride,
                   int32_t cap, double dt, double* part, DevState* st, const FuseOut& fo);
 // integrate.hip
 void launch_kick_drift(hipStream_t s, int32_t mixed, int32_t thermo, int32_t ntiles,
                        const Tile* tiles, const RepDesc* reps, const PairTab* tab,
-                       double4* pos, float4* pos16, double* vel, const void* frc,
+                       double4* pos, int4* pos16, double* vel, const void* frc,
                        const double* xref, int32_t stride, double dt, const double* lam,
                        int32_t* rebuild, double* dmax, DevState* st, int32_t* counts,
                        int32_t nzero);
@@ -249,7 +278,8 @@ struct RedChunk {
 constexpr int32_t kRedChunk = 1024;  // partial blocks per chunk
 constexpr int32_t kPart2 = 8;        // doubles per chunk result
 void launch_reduce_chunks(hipStream_t s, int32_t nchunks, const RedChunk* ch, const double* part,
-                          const double* dmax, int32_t step, int32_t next, double* part2);
+                          const double* dmax, int32_t step, int32_t next, double* part2,
+                          const DevState* st);
 // Where a step's drift maximum comes from and what the reduction does with
 // the rebuild flag (one replica per context when next = 1):
 // src = 0: the kick/drift tile maxima in dmax; src = 1: pend[r], stored by
@@ -278,7 +308,7 @@ void launch_after_build(hipStream_t s, int32_t nrep, int32_t* rebuild, md_obs* o
                         DevState* st);
 void launch_begin_call(hipStream_t s, int32_t nrep, int64_t* kcall, double* lam);
 void launch_apply_lambda(hipStream_t s, int32_t ntiles, const Tile* tiles, int32_t stride,
-                         double* vel, double* lam, int32_t nrep);
+                         double* vel, double* lam, int32_t nrep, const DevState* st);
 
 // analysis.hip
 void launch_msd_ref(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
@@ -288,6 +318,9 @@ void launch_msd(hipStream_t s, int32_t ntiles, int32_t nrep, const Tile* tiles,
                 const double* u0, double* part, double* out);
 void launch_rdf(hipStream_t s, const double4* pos, int32_t off, int32_t n, double L, double rmax,
                 int32_t nbins, unsigned long long* hist);
+// a[0, n) = 0 (a fill kernel rather than hipMemsetAsync, so callers may
+// capture it in a graph)
+void launch_zero_u64(hipStream_t s, unsigned long long* a, int32_t n);
 void launch_rdf_cells(hipStream_t s, int32_t c0, int32_t nc, const int32_t* cell_start,
                       const double4* pos, double L, double rmax, int32_t nbins,
                       unsigned long long* hist);

@@ -14,7 +14,7 @@
 // Mixed lists: the cell offset d = c_i - c_j - s nc in {-1, 0, 1} between
 // the build-time cells of the pair, which turns the 16-byte cell-relative
 // records into the displacement (off_i - off_j) + d * cell side (see
-// make_rec16) with no further decoding.
+// make_recq) with no further decoding.
 #include "stage.h"
 
 #pragma clang fp contract(off)
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
     int32_t cap, const double4* __restrict__ pos_tmp, const double* __restrict__ vel_tmp,
     const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
     int32_t* __restrict__ id, double* __restrict__ xref, uint32_t* __restrict__ nbr,
-    int32_t* __restrict__ ncount, DevState* st, int32_t dcode, float4* __restrict__ pos16) {
+    int32_t* __restrict__ ncount, DevState* st, int32_t dcode, int4* __restrict__ pos16) {
   __shared__ double s_thr[16];
   if (!st->any_rebuild) return;
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kTile) void k_nlist(
   if (pos16) {
     const uint32_t wc = pack_cell(cell_coord(p.x, R.inv_cell, R.nc), cell_coord(p.y, R.inv_cell, R.nc),
                                   cell_coord(p.z, R.inv_cell, R.nc), ti);
-    pos16[i] = make_rec16(p.x, p.y, p.z, wc, R.cside);
+    pos16[i] = make_recq(p.x, p.y, p.z, wc, R.cside, R.qs);
   }
   pos[i] = p;
   xref[i] = p.x;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
     const int32_t* __restrict__ id_tmp, double4* __restrict__ pos, double* __restrict__ vel,
     int32_t* __restrict__ id, double* __restrict__ xref,
     typename std::conditional<TILE, uint16_t, uint32_t>::type* __restrict__ nbr,
-    int32_t* __restrict__ ncount, DevState* st, float4* __restrict__ pos16,
+    int32_t* __restrict__ ncount, DevState* st, int4* __restrict__ pos16,
     const int32_t* __restrict__ cell_tile, const RowTile* __restrict__ rtiles, int32_t dcode,
     int32_t spread) {
   using E = typename std::conditional<TILE, uint16_t, uint32_t>::type;
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
         for (int u = 0; u < 3; ++u) s_l0[w][3 * q + u] += ro;
         ro += s_rowsz[w][q];
       }
-      if (ro > kMaxStaged) atomicOr(&st->err, kErrOverflow);
+      if (ro > kMaxStaged) atomicOr(&st->err, kErrSlots);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -404,7 +404,8 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   for (int32_t h = lane; h < nh; h += 64) {
     const int32_t i = h0 + h;
     const double4 p4 = pos_tmp[i];
-    if (pos16) pos16[i] = make_rec16(p4.x, p4.y, p4.z, pack_cell(qx, qy, qz, (int32_t)p4.w), R.cside);
+    if (pos16)
+      pos16[i] = make_recq(p4.x, p4.y, p4.z, pack_cell(qx, qy, qz, (int32_t)p4.w), R.cside, R.qs);
     pos[i] = p4;
     xref[i] = p4.x;
     xref[stride + i] = p4.y;
@@ -424,7 +425,7 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   const double4* pos_tmp, const double* vel_tmp, const int32_t* id_tmp,
                   double4* pos, double* vel, int32_t* id, double* xref, uint32_t* nbr,
                   int32_t* ncount, DevState* st, int32_t ncells, const int32_t* cell_rep,
-                  int32_t any_single, int32_t any_multi, float4* pos16, int32_t spread) {
+                  int32_t any_single, int32_t any_multi, int4* pos16, int32_t spread) {
   // mixed lists (records present) carry cell offsets instead of images
   const int32_t dcode = pos16 != nullptr;
   if (any_multi) {

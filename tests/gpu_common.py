@@ -77,6 +77,37 @@ def pair_force_sums(eps, sig, rc, types, xw, L, count, ids):
     return out
 
 
+def pair_abs_sums(eps, sig, rc, types, xw, L, count, ids):
+    """Condition numbers of the energy and virial sums: sum over the pairs
+    within r_c (each once) of |V*(r)| and |r f(r)| (shifted-force LJ,
+    Eq. (3)).  A sum of rounded terms errs by at most about n u times the sum
+    of their magnitudes; when the signed total is close to zero (a compressed
+    lattice whose pair energies cancel) these replace it in a relative bar."""
+    eps, sig, rc = (np.asarray(a, dtype=np.float64) for a in (eps, sig, rc))
+    n, cap = ids.shape
+    i = np.repeat(np.arange(n), cap)
+    j = ids.reshape(-1)
+    m = (np.arange(cap)[None, :] < count[:, None]).reshape(-1)
+    i, j = i[m], j[m]
+    d = xw[i] - xw[j]
+    d -= L * np.rint(d / L)
+    r = np.linalg.norm(d, axis=1)
+    a, b = types[i], types[j]
+    e, s, c = eps[a, b], sig[a, b], rc[a, b]
+
+    def v(x):
+        sr6 = (s / x) ** 6
+        return 4.0 * e * (sr6 * sr6 - sr6)
+
+    def dv(x):
+        sr6 = (s / x) ** 6
+        return -(24.0 * e / x) * (2.0 * sr6 * sr6 - sr6)
+    inside = r < c
+    vs = np.where(inside, v(r) - v(c) - (r - c) * dv(c), 0.0)
+    f = np.where(inside, -dv(r) + dv(c), 0.0)
+    return 0.5 * float(np.sum(np.abs(vs))), 0.5 * float(np.sum(np.abs(r * f)))
+
+
 def canonical(count, ids):
     """Rows of ids sorted ascending, padding with a large value past count."""
     n, cap = ids.shape

@@ -551,9 +551,11 @@ def test_large_box_sampled(torch_cuda, path):
 
 def test_67m_mixed_sampled(torch_cuda):
     """One GPU's large share: 67,108,864 particles, mixed precision, after 10
-    steps.  Cell arrays bit-exact over the whole box; forces of 4,096 sampled
-    particles against the oracle's cell-list forces (the full neighbour list,
-    about 50 GB on the host, is checked through those forces)."""
+    steps.  Cell arrays bit-exact over the whole box; forces of 131,072
+    sampled particles against the oracle's cell-list forces, and the total
+    potential energy and virial against the oracle's sums over all particles
+    (the full neighbour list, about 50 GB on the host, is checked through the
+    forces it produces)."""
     say("case 67M mixed")
     from paper_1105_5613_amd import System
     n = 67108864
@@ -569,16 +571,23 @@ def test_67m_mixed_sampled(torch_cuda):
     assert sysm.replica_info(0)["nc"] == nc == 136
     assert np.array_equal(gcs, cs) and np.array_equal(gorder, order)
     del gcs, gorder, cs, order
+    say("  cells bit-exact")
     sysm.forces()
     F = sysm.get_forces().cpu().numpy()
-    sel = np.random.default_rng(5).choice(n, 4096, replace=False)
-    Fo, _, _ = oracle.forces_cells(p, x, s["type"], s["L"], sel=sel)
-    frms = float(np.sqrt(np.mean(np.sum(F.astype(np.float64) ** 2, axis=1))))
-    d = np.linalg.norm(F[sel].astype(np.float64) - Fo, axis=1)
-    e = float(np.max(d / np.maximum(np.linalg.norm(Fo, axis=1), frms)))
-    say(f"  sampled force error {e:.3e}")
-    assert e <= 1e-5
     ob = sysm.observables()[0]
+    sysm.close()
+    Fo, pe_i, w_i = oracle.forces_cells(p, x, s["type"], s["L"])
+    say("  oracle forces done")
+    sel = np.random.default_rng(5).choice(n, 131072, replace=False)
+    frms = float(np.sqrt(np.mean(np.sum(F.astype(np.float64) ** 2, axis=1))))
+    d = np.linalg.norm(F[sel].astype(np.float64) - Fo[sel], axis=1)
+    e = float(np.max(d / np.maximum(np.linalg.norm(Fo[sel], axis=1), frms)))
+    pe, w = float(np.sum(pe_i)), float(np.sum(w_i))
+    say(f"  sampled force error {e:.3e}; pe {ob['pe']:.10e} vs {pe:.10e}, "
+        f"virial {ob['virial']:.10e} vs {w:.10e}")
+    assert e <= 1e-5
+    assert ob["pe"] == pytest.approx(pe, rel=1e-6)
+    assert ob["virial"] == pytest.approx(w, rel=1e-6)
     assert np.isfinite(ob["E"]) and ob["n_rebuild"] >= 2
 
 
@@ -685,11 +694,17 @@ def test_torch_allocator(torch_cuda):
 
 
 def test_checkpoint_resume(torch_cuda):
-    """200 steps straight vs 100 + get_state/set_state + 100."""
+    """200 steps straight vs 100 + get_state/set_state + 100.  The restored
+    context builds its lists on the restored state at step 100, so the
+    straight run rebuilds there too (md_build_cells): then the two runs do
+    the same arithmetic and must agree bit for bit (FP64 path)."""
     say("case checkpoint")
     a, s = make_system(torch_cuda, 4000, 6)
-    a.step(200)
+    a.step(100)
+    a.build_cells()
+    a.step(100)
     xa, va, ia = (t.cpu().numpy() for t in a.get_state())
+    Fa = a.get_forces().cpu().numpy()
     b, _ = make_system(torch_cuda, 4000, 6)
     b.step(100)
     x, v, img = b.get_state()
@@ -697,7 +712,9 @@ def test_checkpoint_resume(torch_cuda):
     c.set_state(x, v, s["type"])
     c.step(100)
     xc, vc, ic = (t.cpu().numpy() for t in c.get_state())
-    ua = xa + ia * s["L"]
-    uc = xc + (ic + img.cpu().numpy()) * s["L"]
-    assert np.max(np.abs(ua - uc)) < 1e-8
-    assert np.max(np.abs(va - vc)) < 1e-8
+    Fc = c.get_forces().cpu().numpy()
+    assert np.array_equal(xa, xc)
+    assert np.array_equal(va, vc)
+    assert np.array_equal(ia, ic + img.cpu().numpy())
+    assert np.array_equal(Fa, Fc)
+    assert a.observables()[0]["E"] == c.observables()[0]["E"]
