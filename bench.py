@@ -108,26 +108,58 @@ def mixture():
     return initconf.mixture_tables()
 
 
-LOG_EVERY = 10  # observables logged every 10 timed steps (energy drift)
+LOG_EVERY = 10  # observables logged every 10 timed steps
+DRIFT_STEPS = 1100  # the NVE window of the drift figure, whatever --steps is
+DRIFT_BURN = 100
+FORCE_SAMPLE = 4096  # particles whose forces are checked against the oracle
 
 
-def energy_drift(E, n: int, warmup: int):
-    """|least-squares slope of E/N| per 1,000 steps over the logged timed steps
-    from step 100 of the run on (100-step burn-in); None when fewer than 900
-    steps follow the burn-in (a short window measures the start-up transient,
-    not the drift)."""
+def energy_drift(E, n: int, burn: int = DRIFT_BURN):
+    """Energy drift D of an NVE run whose total energy E was logged after
+    every step 1, 2, ...: |least-squares slope of E/N| per 1,000 steps over
+    the steps after a burn-in (the start-up transient of a lattice start).
+    Also the largest |E - E(burn)|/N.  None when fewer than 900 steps follow
+    the burn-in."""
     import numpy as np
     e = np.asarray(E, dtype=np.float64) / n
-    step = warmup + LOG_EVERY * (1 + np.arange(len(e), dtype=np.float64))
-    if step[-1] - 100 < 900:
+    step = 1.0 + np.arange(len(e), dtype=np.float64)
+    keep = step >= burn
+    if len(e) - burn < 900:
         return None
-    keep = step >= 100
-    return float(abs(np.polyfit(step[keep], e[keep], 1)[0]) * 1000.0)
+    d = float(abs(np.polyfit(step[keep], e[keep], 1)[0]) * 1000.0)
+    return {"D": d, "max_abs_dE_per_particle": float(np.max(np.abs(e[keep] - e[keep][0])))}
+
+
+def floored_force_error(F_sel, Fo_sel, frms: float) -> float:
+    """e = max_i |F_i - F_i^ref| / max(|F_i^ref|, F_rms) over the sample."""
+    import numpy as np
+    d = np.linalg.norm(np.asarray(F_sel, dtype=np.float64) - Fo_sel, axis=1)
+    return float(np.max(d / np.maximum(np.linalg.norm(Fo_sel, axis=1), frms)))
+
+
+def run_drift(precision: int, inputs, path: int = 1, potential: int = 0, global_rc=None,
+              dt: float = 0.005):
+    """D over DRIFT_STEPS NVE steps of a fresh context from the form's initial
+    state (energies every step), so the figure does not depend on --steps."""
+    from paper_1105_5613_amd import System, make_params
+    import initconf
+    eps, sig, rc, mass = initconf.mixture_tables(global_rc=global_rc)
+    p = make_params(eps, sig, rc, mass, skin=0.3, dt=dt, precision=precision, path=path,
+                    potential=potential)
+    n = inputs["n"]
+    sysm = System(p, [n], [inputs["L"]])
+    sysm.set_state(inputs["x"], inputs["v"], inputs["type"])
+    lg = sysm.step(DRIFT_STEPS, log_every=1)
+    sysm.close()
+    out = energy_drift(lg["E"][:, 0], n)
+    out["window"] = f"steps {DRIFT_BURN}..{DRIFT_STEPS} of an NVE run from the initial state, " \
+                    f"dt {dt}, E logged every step"
+    return out
 
 
 def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_every: int,
                path: int = 1, potential: int = 0, global_rc=None, dt: float = 0.005, T0=None,
-               graph_steps: int = 0):
+               graph_steps: int = 0, sample_forces: bool = False):
     from paper_1105_5613_amd import System, make_params
     import initconf
     eps, sig, rc, mass = initconf.mixture_tables(global_rc=global_rc)
@@ -148,12 +180,22 @@ def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_ever
     sysm.profile(0)
     nbar, nmax = (0.0, 0) if path == 3 else sysm.list_stats()
     obs = sysm.observables()[0]
+    sample = None
+    if sample_forces:
+        # the forces on the state the timed run reached, for the CPU leg's
+        # comparison with the oracle (a sample of FORCE_SAMPLE particles)
+        import numpy as np
+        x = sysm.get_state()[0].cpu().numpy()
+        sysm.forces()
+        F = sysm.get_forces().cpu().numpy().astype(np.float64)
+        sel = np.random.default_rng(11).choice(n, FORCE_SAMPLE, replace=False)
+        sample = {"x": x, "type": inputs["type"], "L": inputs["L"], "sel": sel,
+                  "F_sel": F[sel], "frms": float(np.sqrt(np.mean(np.sum(F * F, axis=1))))}
     sysm.close()
     return {"wall_s": wall, "rate": n * steps / wall, "ms_per_step": 1e3 * wall / steps,
             "force_ms_avg": prof["force_ms"] / max(prof["force_launches"], 1),
             "force_launches_timed": prof["force_launches"], "nbar": nbar, "nmax": nmax,
-            "rebuilds": obs["n_rebuild"], "steps_total": obs["step"],
-            "drift": None if T0 is not None else energy_drift(lg["E"][:, 0], n, warmup),
+            "rebuilds": obs["n_rebuild"], "steps_total": obs["step"], "sample": sample,
             "tuned": {"tpp": tuned["tpp"], "unroll": tuned["unroll"]}}
 
 
@@ -211,6 +253,23 @@ def run_one_at_a_time(torch, systems, temps, steps: int):
     for c, _ in ctxs:
         c.close()
     return {"rate": sum(s["n"] for s in systems) * steps / wall, "steps": steps}
+
+
+def oracle_force_errors(samples):
+    """The CPU leg's accuracy check: for each GPU form, the oracle's forces on
+    the sampled particles of the state the form reached, and the floored
+    error e of the GPU forces against them."""
+    import oracle
+    eps, sig, rc, mass = mixture()
+    p = oracle.make_params(eps, sig, rc, mass, skin=0.3)
+    out = {}
+    for form, sm in samples.items():
+        Fo, _, _ = oracle.forces_cells(p, sm["x"], sm["type"], sm["L"], sel=sm["sel"])
+        out[form] = {"e": floored_force_error(sm["F_sel"], Fo, sm["frms"]),
+                     "sample": f"{len(sm['sel'])} random particles of the state after the "
+                               "timed steps, FP64 oracle cell-list forces",
+                     "norm": "max_i |dF_i| / max(|F_i|, F_rms)"}
+    return out
 
 
 def cpu_baseline(inputs, nsteps: int, nsteps_1t: int = 4):
@@ -341,10 +400,11 @@ def main():
             continue
         log(f"timing form {f}: {args.steps} steps after {args.warmup} warmup")
         res[f] = run_single(torch, 1 if f == "mixed" else 0, inputs, args.steps, args.warmup,
-                            args.profile_every)
+                            args.profile_every, sample_forces=not args.no_cpu_baseline)
+        res[f]["drift"] = run_drift(1 if f == "mixed" else 0, inputs)
         log(f"  {f}: {res[f]['rate']:.4e} particle-steps/s, {res[f]['ms_per_step']:.4f} ms/step, "
             f"force {res[f]['force_ms_avg']:.4f} ms, nbar {res[f]['nbar']:.2f}, "
-            f"rebuilds {res[f]['rebuilds']}, drift {res[f]['drift']}")
+            f"rebuilds {res[f]['rebuilds']}, drift {res[f]['drift']['D']:.3e}")
     forms_out = {}
     for f, r in res.items():
         b = force_bytes_per_particle(r["nbar"], f == "mixed")
@@ -361,7 +421,8 @@ def main():
                                 r["nbar"], f == "mixed",
                                 r["rebuilds"] / max(r["steps_total"], 1)) / 1e9 / HBM_PEAK_GBS, 4),
                         "mean_list_length": round(r["nbar"], 3), "rebuilds": r["rebuilds"],
-                        "energy_drift_per_particle_per_1000_steps": r["drift"],
+                        "energy_drift_per_particle_per_1000_steps": r["drift"]["D"],
+                        "energy_drift": r["drift"],
                         "tuned": r["tuned"]}
     if "fp64" in res and "mixed" in res:
         forms_out["speedup_mixed_vs_fp64"] = round(res["mixed"]["rate"] / res["fp64"]["rate"], 4)
@@ -371,6 +432,8 @@ def main():
         big = initconf.fcc_system(nl, seed=3, temperature=2.0)
         log(f"timing the large mixed form: {args.large_steps} steps after 20 warmup")
         rl = run_single(torch, 1, big, args.large_steps, 20, args.profile_every)
+        log(f"  large mixed drift window: {DRIFT_STEPS} NVE steps")
+        rl["drift"] = run_drift(1, big)
         del big
         bl = force_bytes_per_particle(rl["nbar"], True)
         ach = nl * bl / (max(rl["force_ms_avg"], 1e-12) * 1e-3) / 1e9
@@ -383,13 +446,14 @@ def main():
             "force_ms_avg": round(rl["force_ms_avg"], 4), "force_achieved_gbs": round(ach, 1),
             "force_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
             "mean_list_length": round(rl["nbar"], 3), "rebuilds": rl["rebuilds"],
-            "energy_drift_per_particle_per_1000_steps": rl["drift"],
-            "tuned": rl["tuned"]}
+            "energy_drift_per_particle_per_1000_steps": rl["drift"]["D"],
+            "energy_drift": rl["drift"], "tuned": rl["tuned"]}
     if "small" in forms:
         log(f"timing the 4000-particle box (FP64): {args.steps} steps, direct and in graphs")
         small = initconf.fcc_system(4000, seed=1, temperature=2.0)
         rd = run_single(torch, 0, small, args.steps, args.warmup, 0)
         rg = run_single(torch, 0, small, args.steps, args.warmup, 0, graph_steps=100)
+        dsmall = run_drift(0, small)
         log(f"  small: direct {rd['rate']:.4e}, graphs {rg['rate']:.4e} particle-steps/s")
         forms_out["small_fp64"] = {
             "workload": "lj4000: 4,000-particle binary LJ mixture (FCC n=10, L=14.938, 5 cells "
@@ -397,10 +461,12 @@ def main():
             "value_direct": round(rd["rate"], 1), "ms_per_step_direct": round(rd["ms_per_step"], 5),
             "value_graphs_100": round(rg["rate"], 1),
             "ms_per_step_graphs_100": round(rg["ms_per_step"], 5),
-            "rebuilds": rd["rebuilds"]}
+            "rebuilds": rd["rebuilds"],
+            "energy_drift_per_particle_per_1000_steps": dsmall["D"], "energy_drift": dsmall}
     if "cells" in forms:
         log(f"timing the list-free cell path (FP64): {args.steps} steps")
         rcell = run_single(torch, 0, inputs, args.steps, args.warmup, args.profile_every, path=3)
+        rcell["drift"] = run_drift(0, inputs, path=3)
         log(f"  cell path: {rcell['rate']:.4e} particle-steps/s, {rcell['ms_per_step']:.4f} ms/step, "
             f"force {rcell['force_ms_avg']:.4f} ms")
         forms_out["cells_fp64"] = {
@@ -408,7 +474,8 @@ def main():
                         "27-cell stencil searched in every force launch)",
             "value": round(rcell["rate"], 1), "ms_per_step": round(rcell["ms_per_step"], 5),
             "force_ms_avg": round(rcell["force_ms_avg"], 5), "rebuilds": rcell["rebuilds"],
-            "energy_drift_per_particle_per_1000_steps": rcell["drift"]}
+            "energy_drift_per_particle_per_1000_steps": rcell["drift"]["D"],
+            "energy_drift": rcell["drift"]}
         if "fp64" in res:
             forms_out["cells_fp64"]["rate_vs_list_fp64"] = round(rcell["rate"] / res["fp64"]["rate"], 4)
     if "soft" in forms:
@@ -416,6 +483,7 @@ def main():
         soft_in = initconf.fcc_system(n, seed=6, temperature=0.5)
         rs = run_single(torch, 0, soft_in, args.steps, args.warmup, args.profile_every,
                         potential=1, global_rc=1.2, dt=0.001, T0=0.5)
+        dsoft = run_drift(0, soft_in, potential=1, global_rc=1.2, dt=0.001)
         del soft_in
         log(f"  soft sphere: {rs['rate']:.4e} particle-steps/s, {rs['ms_per_step']:.4f} ms/step")
         forms_out["soft_fp64"] = {
@@ -423,7 +491,10 @@ def main():
                         "(velocity rescale), rc=1.2 for every pair, dt 0.001, skin 0.3, FP64",
             "value": round(rs["rate"], 1), "ms_per_step": round(rs["ms_per_step"], 5),
             "force_ms_avg": round(rs["force_ms_avg"], 5),
-            "mean_list_length": round(rs["nbar"], 3), "rebuilds": rs["rebuilds"]}
+            "mean_list_length": round(rs["nbar"], 3), "rebuilds": rs["rebuilds"],
+            "nve_energy_drift_per_particle_per_1000_steps": dsoft["D"],
+            "nve_energy_drift": dict(dsoft, note="the same box and start run NVE (the timed "
+                                     "run is canonical, where energy is not conserved)")}
     if "batched" in forms:
         log(f"timing batched replicas: {args.replicas} boxes, {args.batched_steps} steps")
         systems, temps = replica_inputs(args.replicas)
@@ -477,6 +548,12 @@ def main():
         log(f"timing the CPU oracle: {args.cpu_steps} steps")
         cpu = cpu_baseline(inputs, args.cpu_steps)
         log(f"  oracle: {cpu['value']:.4e} particle-steps/s on {cpu['cores']} threads")
+        samples = {f: r["sample"] for f, r in res.items() if r.get("sample") is not None}
+        if samples:
+            log(f"oracle forces on {FORCE_SAMPLE} sampled particles per form")
+            for f, er in oracle_force_errors(samples).items():
+                forms_out[f]["force_error_vs_oracle"] = er
+                log(f"  {f}: e = {er['e']:.3e}")
     out = {
         "metric": METRIC, "value": None if head is None else round(head["rate"], 1),
         "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -31,14 +31,24 @@ def test_step_bytes_add_the_rebuild_share():
 
 
 def test_energy_drift_slope_and_short_window():
-    # E/N rising by 2e-5 per 1,000 steps plus a constant: the slope comes back
-    n, warmup = 1000, 50
-    k = np.arange(200)
-    step = warmup + bench.LOG_EVERY * (1 + k)
+    # E/N rising by 2e-5 per 1,000 steps plus a constant, logged every step:
+    # the slope after the burn-in comes back, with the largest excursion
+    n = 1000
+    step = 1.0 + np.arange(1100)
     E = n * (3.0 + 2e-8 * step)
-    assert bench.energy_drift(E, n, warmup) == pytest.approx(2e-5, rel=1e-6)
+    E[:50] += n * 1e-3  # a start-up transient inside the burn-in is ignored
+    d = bench.energy_drift(E, n)
+    assert d["D"] == pytest.approx(2e-5, rel=1e-6)
+    assert d["max_abs_dE_per_particle"] == pytest.approx(2e-8 * 1000, rel=1e-6)
     # fewer than 900 steps after the 100-step burn-in: no figure
-    assert bench.energy_drift(E[:50], n, warmup) is None
+    assert bench.energy_drift(E[:900], n) is None
+
+
+def test_floored_force_error():
+    F = np.array([[1.0, 0.0, 0.0], [0.0, 10.0, 0.0]])
+    Fo = np.array([[1.0, 0.0, 1e-6], [0.0, 10.0 + 1e-5, 0.0]])
+    # particle 0: 1e-6 / max(1, 5); particle 1: 1e-5 / max(10.00001, 5)
+    assert bench.floored_force_error(F, Fo, 5.0) == pytest.approx(1e-5 / (10.0 + 1e-5), rel=1e-9)
 
 
 def test_counter_traffic_needs_the_current_kernel_source(tmp_path, monkeypatch):
