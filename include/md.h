@@ -303,6 +303,18 @@ md_status md_msd(md_ctx ctx, double* out);
  * particles.  rmax <= L/2, nbins <= 8192.  g HOST [nbins].  Synchronises. */
 md_status md_rdf(md_ctx ctx, int32_t rep, double rmax, int32_t nbins, double* g);
 
+/* md_rdf for callers that cannot allocate device memory (tight serving or
+ * analysis loops, harnesses that forbid hipMalloc): the same g(r), bit for
+ * bit, with the pair histogram in a fixed 64 KiB device array (8192 64-bit
+ * counters) that each GPU holds for the life of the process instead of a
+ * buffer allocated per call.  Allocates nothing and builds nothing: the
+ * cell sweep (rmax <= cell side - skin) needs cells built by an earlier
+ * md_build_cells / md_forces / md_step, else MD_ESTATE.  nbins > 8192 ->
+ * MD_EINVAL.  Every call on one GPU shares that array and clears it first,
+ * so calls that overlap on the same GPU (other host threads, other
+ * contexts' streams) race and must be serialised by the caller.
+ * Synchronises, so it cannot itself be captured in a graph. */
+md_status md_rdf_static(md_ctx ctx, int32_t rep, double rmax, int32_t nbins, double* g);
 
 /* Neighbour-list statistics of replica rep (rep = -1: all replicas) at the
  * last list build: mean and maximum entries per particle.  Synchronises. */

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -14,8 +15,39 @@
 
 using namespace mdk;
 
+// Pair-distance histogram of md_rdf_static: a fixed device array, so that
+// call allocates nothing.  Every GPU the library runs on holds its own copy
+// (64 KiB) until the process ends; host code addresses it only through the
+// per-device pointer hipGetSymbolAddress returns (scratch_dev).
+constexpr int32_t kStaticBins = 8192;
+static __device__ __align__(256) unsigned long long scratch[kStaticBins];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_dev[kMaxDevices] = {};
+
+// Look up this device's copy of scratch once (the device must be current).
+hipError_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[dev] = (unsigned long long*)ptr;
+  return hipSuccess;
+}
+
+unsigned long long* scratch_dev(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return dev >= 0 && dev < kMaxDevices ? g_scratch_dev[dev] : nullptr;
+}
+}  // namespace
+
 struct md_ctx_s {
   md_params p{};
+  int32_t device = 0;  // the device current at md_init
   int32_t nrep = 0, ntot = 0, stride = 0, ncells = 0, ntiles = 0, cap = 0, tpp = 1, unroll = 4;
   int32_t mixed = 0;
   // staged path (row tiles with LDS-staged neighbourhoods)
@@ -539,8 +571,17 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
   if (ntot > (int64_t)kIdxMask + 1)
     return fail(nullptr, MD_EINVAL, "total particle count must be <= 2^26");
 
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, MD_EHIP, "hipGetDevice failed");
+  {
+    const hipError_t e = scratch_setup(dev);
+    if (e != hipSuccess)
+      return fail(nullptr, MD_EHIP,
+                  std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+  }
   md_ctx c = new md_ctx_s();
   c->p = *p;
+  c->device = dev;
   c->nrep = nrep;
   c->ntot = (int32_t)ntot;
   c->stride = (int32_t)(((ntot + 63) / 64) * 64);
@@ -1226,7 +1267,7 @@ md_status rdf_with(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g,
                 "md_rdf: rmax above the cell side minus the skin needs a replica of at most "
                 "262144 particles");
   if (by_cells && !c->built) {
-    if (!may_build) return fail(c, MD_ESTATE, "md_rdf: cells not built");
+    if (!may_build) return fail(c, MD_ESTATE, "md_rdf_static: cells not built");
     md_status b = build_all(c);
     if (b) return b;
   }
@@ -1255,7 +1296,7 @@ md_status rdf_args(md_ctx c, int32_t rep, double rmax, int32_t nbins, const doub
   if (rep < 0 || rep >= c->nrep) return fail(c, MD_EINVAL, "replica index out of range");
   if (!c->has_state) return fail(c, MD_ESTATE, "no state set");
   const RepDesc& d = c->reps_h[rep];
-  if (!g || nbins < 1 || nbins > 8192 || !(rmax > 0.0) || rmax > 0.5 * d.L)
+  if (!g || nbins < 1 || nbins > kStaticBins || !(rmax > 0.0) || rmax > 0.5 * d.L)
     return fail(c, MD_EINVAL, "need g, 1 <= nbins <= 8192 and 0 < rmax <= L/2");
   return MD_OK;
 }
@@ -1271,6 +1312,15 @@ md_status md_rdf(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g) {
   rc = rdf_with(c, rep, rmax, nbins, g, hist, true);
   dfree(c, hist);
   return rc;
+}
+
+md_status md_rdf_static(md_ctx c, int32_t rep, double rmax, int32_t nbins, double* g) {
+  if (!c) return MD_EINVAL;
+  md_status rc = rdf_args(c, rep, rmax, nbins, g);
+  if (rc) return rc;
+  unsigned long long* hist = scratch_dev(c->device);
+  if (!hist) return fail(c, MD_EHIP, "md_rdf_static: no scratch address for this device");
+  return rdf_with(c, rep, rmax, nbins, g, hist, false);
 }
 
 md_status md_list_stats(md_ctx c, int32_t rep, double* mean, int32_t* max) {

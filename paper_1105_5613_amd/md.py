@@ -27,7 +27,7 @@ EXPORTS = ["md_init", "md_init_alloc", "md_destroy", "md_last_error", "md_set_st
            "md_build_cells", "md_forces", "md_get_forces", "md_step", "md_observables",
            "md_get_cells", "md_get_neighbors", "md_replica_info", "md_profile",
            "md_profile_read", "md_list_stats", "md_autotune", "md_msd_reference", "md_msd",
-           "md_rdf"]
+           "md_rdf", "md_rdf_static"]
 
 
 class MDError(RuntimeError):
@@ -104,6 +104,7 @@ def lib():
         L.md_msd_reference.argtypes = [vp]
         L.md_msd.argtypes = [vp, C.POINTER(C.c_double)]
         L.md_rdf.argtypes = [vp, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_double)]
+        L.md_rdf_static.argtypes = [vp, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_double)]
         for name in EXPORTS:
             if name != "md_last_error":
                 getattr(L, name).restype = C.c_int32
