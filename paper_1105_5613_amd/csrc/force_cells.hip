@@ -114,7 +114,9 @@ __global__ __launch_bounds__(kCellHomes) __attribute__((amdgpu_waves_per_eu(6)))
   __shared__ StageLayout S;
   __shared__ PairLds<T> P;
   __shared__ double s_mass[4];
-  __shared__ uint32_t s_hit[kHitBuf][kCellHomes];  // particle index | piece << 26
+  // hit = offset of the particle in its piece | piece << 27 (offsets are
+  // below the piece's length, so any particle count fits)
+  __shared__ uint32_t s_hit[kHitBuf][kCellHomes];
   if (halted(st)) {  // an overflowed list build halts the queued steps (kHalt)
     if (blockIdx.x == 0 && threadIdx.x == 0) st->any_rebuild = 0;
     return;
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(kCellHomes) __attribute__((amdgpu_waves_per_eu(6)))
         rc2 = tj == 0 ? rc2_0 : (tj == 1 ? rc2_1 : (tj == 2 ? rc2_2 : rc2_3));
       }
       const bool hit = SELF ? (j != i && r2 < rc2) : r2 < rc2;
-      if (hit) s_hit[cnt++][threadIdx.x] = (uint32_t)j | ((uint32_t)pc << 26);
+      if (hit) s_hit[cnt++][threadIdx.x] = (uint32_t)(j - S.pc_g[pc]) | ((uint32_t)pc << 27);
     };
     auto flush = [&]() {
       int32_t mx = cnt;
@@ -186,8 +188,8 @@ __global__ __launch_bounds__(kCellHomes) __attribute__((amdgpu_waves_per_eu(6)))
       for (int32_t k = 0; k < mx; ++k) {
         if (k < cnt) {
           const uint32_t e = s_hit[k][threadIdx.x];
-          const int32_t pc = (int32_t)(e >> 26);
-          const double4 q = pos[e & kIdxMask];
+          const int32_t pc = (int32_t)(e >> 27);
+          const double4 q = pos[S.pc_g[pc] + (int32_t)(e & 0x07ffffffu)];
           pair_force<T>(P, p, ti, q.x + S.pc_sx[pc], q.y + S.pc_sy[pc], q.z + S.pc_sz[pc],
                         (int32_t)q.w, a);
         }

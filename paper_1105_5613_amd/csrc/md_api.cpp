@@ -568,8 +568,15 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
       return fail(nullptr, MD_EBOX, "box side L must be >= 2 (max rc + skin)");
     ntot += n[r];
   }
-  if (ntot > (int64_t)kIdxMask + 1)
-    return fail(nullptr, MD_EINVAL, "total particle count must be <= 2^26");
+  // list entries carry a 26-bit particle index; the list-free path keeps no
+  // list and indexes particles with 32-bit integers
+  if (p->path != MD_PATH_CELLS && ntot > (int64_t)kIdxMask + 1)
+    return fail(nullptr, MD_EINVAL,
+                "total particle count must be <= 2^26 on the list paths (the list-free "
+                "path takes up to 2^30)");
+  // SoA components are addressed as stride + i in 32-bit arithmetic
+  if (ntot > (int64_t)1 << 30)
+    return fail(nullptr, MD_EINVAL, "total particle count must be <= 2^30");
 
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, MD_EHIP, "hipGetDevice failed");
@@ -808,7 +815,7 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
   } else {
     ALLOC(c->nbr, list_elems(c->ntot, c->cap));
   }
-  ALLOC(c->ncount, N);
+  if (!c->cells) ALLOC(c->ncount, N);  // list lengths (the list-free path has none)
   ALLOC(c->part, 4 * std::max((size_t)c->ntiles * 8, (size_t)c->nrt));
   ALLOC(c->rebuild, (size_t)nrep);
   ALLOC(c->dmax, (size_t)c->ntiles);

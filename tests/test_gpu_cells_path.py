@@ -116,3 +116,49 @@ def test_cells_path_1m_sampled(torch_cuda):
         e = float(np.max(d / np.maximum(np.linalg.norm(Fo, axis=1), frms)))
         say(f"  precision {precision}: sampled force error {e:.3e}")
         assert e <= (1e-12 if precision == 0 else 1e-5)
+
+
+def test_cells_path_beyond_list_index_range(torch_cuda):
+    """The list-free path keeps no neighbour list, so it is not bound by the
+    26-bit index of list entries: a 134,217,728-particle (2^27) box, FP64,
+    after 3 steps.  Cell arrays bit-exact over the whole box; forces of 4,096
+    sampled particles and the energy and virial totals against the oracle's
+    cell-list sums over all particles.  The list paths refuse the box."""
+    from paper_1105_5613_amd import MDError, System
+    n = 1 << 27
+    say(f"case cell path n={n}")
+    s = initconf.fcc_system(n, seed=61, temperature=2.0)
+    say("  inputs generated")
+    with pytest.raises(MDError) as ex:
+        System(lib_params(path=1), [n], [s["L"]])
+    assert ex.value.code == -1
+    sysm = System(lib_params(path=3), [n], [s["L"]])
+    sysm.set_state(s["x"], s["v"], s["type"])
+    sysm.step(3)
+    x = sysm.get_state()[0].cpu().numpy()
+    sysm.build_cells()
+    sysm.forces()
+    F = sysm.get_forces().cpu().numpy()
+    ob = sysm.observables()[0]
+    gcs, gorder = sysm.get_cells(0)
+    sysm.close()
+    del s["v"]
+    say("  GPU done")
+    p = oracle_params()
+    _, _, _, cs, order, nc = oracle.build_cells(p, x, s["L"])
+    assert nc == 172
+    assert np.array_equal(gcs, cs) and np.array_equal(gorder, order)
+    del gcs, gorder, cs, order
+    say("  cells bit-exact")
+    Fo, pe_i, w_i = oracle.forces_cells(p, x, s["type"], s["L"])
+    say("  oracle forces done")
+    sel = np.random.default_rng(7).choice(n, 4096, replace=False)
+    frms = float(np.sqrt(np.mean(np.sum(F * F, axis=1))))
+    d = np.linalg.norm(F[sel] - Fo[sel], axis=1)
+    e = float(np.max(d / np.maximum(np.linalg.norm(Fo[sel], axis=1), frms)))
+    pe, w = float(np.sum(pe_i)), float(np.sum(w_i))
+    say(f"  sampled force error {e:.3e}; pe rel {abs(ob['pe'] - pe) / abs(pe):.2e}, "
+        f"virial rel {abs(ob['virial'] - w) / abs(w):.2e}")
+    assert e <= 1e-12
+    assert ob["pe"] == pytest.approx(pe, rel=1e-12)
+    assert ob["virial"] == pytest.approx(w, rel=1e-12)
