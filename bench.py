@@ -37,6 +37,14 @@ METRIC = "particle-steps/sec on 1 MI355X + % HBM roofline; mixed/batched vs plai
 HBM_PEAK_GBS = 8000.0
 FORCE_SRC = os.path.join(ROOT, "paper_1105_5613_amd", "csrc", "force.hip")
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "force_counters.json")
+FP64_OPS_JSON = os.path.join(ROOT, "profiles", "fp64_ops.json")
+FP64_PEAK_TFLOPS = 78.6
+CSRC = os.path.join(ROOT, "paper_1105_5613_amd", "csrc")
+# kernels whose FP64 operation counts the bench turns into FLOP/s: name
+# fragment in the counter output -> source file
+FLOP_KERNELS = {"cells_fp64": ("k_force_cells<false", "force_cells.hip"),
+                "nlist_fp64": ("k_nlist_cells<4, 1024, false", "nlist.hip"),
+                "force_fp64": ("k_force<false, 2", "force.hip")}
 COPY_BYTES = 1 << 30
 
 
@@ -85,8 +93,23 @@ def copy_gbs(torch) -> float:
     return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
 
 
-def src_sha() -> str:
-    return hashlib.sha256(open(FORCE_SRC, "rb").read()).hexdigest()
+def src_sha(path: str = FORCE_SRC) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def fp64_flops_per_particle(key: str):
+    """FP64 FLOP per particle of one launch of a kernel, from the committed
+    rocprofv3 operation counts (64 lanes x (ADD + MUL + 2 FMA + TRANS) wave
+    instructions per dispatch, over the particles of the measured box), or
+    None when the kernel's source changed since the counters were taken."""
+    if not os.path.exists(FP64_OPS_JSON):
+        return None
+    with open(FP64_OPS_JSON) as f:
+        d = json.load(f)
+    ent = d.get("kernels", {}).get(key)
+    if not ent or ent.get("src_sha256") != src_sha(os.path.join(CSRC, FLOP_KERNELS[key][1])):
+        return None
+    return ent["flop_per_dispatch"] / ent["particles"]
 
 
 def counters_traffic(key: str):
@@ -207,14 +230,30 @@ def replica_inputs(nrep: int):
     return systems, temps
 
 
+TUNE_SKINS = (0.2, 0.3, 0.4)
+
+
 def run_batched(torch, precision: int, systems, temps, steps: int, warmup: int,
-                graph_steps: int):
+                graph_steps: int, tune: bool = True):
+    """The batch in one context.  tune: first pick the kernel path, the skin
+    (which sets the cell side, the smallest the 27-cell stencil allows for
+    it), the staged tile length and the force variant by short trial runs of
+    the same batch (paper_1105_5613_amd.tune, not timed)."""
     import initconf
     from paper_1105_5613_amd import System, make_params
     eps, sig, rc, mass = mixture()
     x, v, t, n, L = initconf.concat_replicas(systems)
     p = make_params(eps, sig, rc, mass, skin=0.3, dt=0.005, precision=precision,
                     graph_steps=graph_steps)
+    choice = None
+    if tune:
+        from paper_1105_5613_amd import tune as tuner
+        p, rep_ = tuner.autotune(p, n, L, x, v, t, T0=temps, steps=60, warmup=20,
+                                 skins=TUNE_SKINS, tile_cells=(0,), use_cache=False,
+                                 cache_path=None)
+        choice = {"choice": rep_.get("choice"),
+                  "trials": [{**tr["choice"], "rate": round(tr["rate"], 1)}
+                             for tr in rep_.get("trials", [])]}
     sysm = System(p, n, L)
     sysm.set_state(x, v, t)
     sysm.step(warmup, T0=temps)
@@ -230,7 +269,9 @@ def run_batched(torch, precision: int, systems, temps, steps: int, warmup: int,
     terr = max(abs(o["T"] - tt) / tt for o, tt in zip(obs, temps))
     return {"rate": sum(n) * steps / wall, "ms_per_step": 1e3 * wall / steps,
             "particles": sum(n), "max_rel_T_error": terr,
-            "tuned": {"tpp": tuned["tpp"], "unroll": tuned["unroll"]}}
+            "tuned": {"path": int(p.path), "skin": float(p.skin), "tpp": tuned["tpp"],
+                      "unroll": tuned["unroll"]},
+            "tuner": choice}
 
 
 def run_one_at_a_time(torch, systems, temps, steps: int):
@@ -298,6 +339,20 @@ def cpu_baseline(inputs, nsteps: int, nsteps_1t: int = 4):
                            "sample": f"the next {nsteps_1t} steps on one thread, {wall1:.1f} s"}}
 
 
+def cells_flops(n: int, force_ms: float):
+    """The list-free force kernel is bound by FP64 vector issue, not HBM: its
+    FP64 FLOP rate (committed operation counts per particle x n / the
+    measured mean launch time) against the 78.6 TFLOP/s FP64 vector peak."""
+    fpp = fp64_flops_per_particle("cells_fp64")
+    if fpp is None or force_ms <= 0:
+        return None
+    tf = fpp * n / (force_ms * 1e-3) / 1e12
+    return {"bound": "fp64 vector alu", "flop_per_particle": round(fpp, 1),
+            "achieved_tflops": round(tf, 2), "peak_tflops": FP64_PEAK_TFLOPS,
+            "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+            "source": "profiles/fp64_ops.json (rocprofv3 SQ_INSTS_VALU_*_F64)"}
+
+
 def calibrate_copy(torch):
     """A plain device-to-device copy of COPY_BYTES (counter calibration)."""
     a = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
@@ -318,6 +373,33 @@ def _counter_rows(d, name_part):
                 out.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(
                     float(r["Counter_Value"]))
     return out
+
+
+def fp64_ops_summary(args):
+    """FP64 operation counts (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64, wave
+    instructions per dispatch) of the kernels in FLOP_KERNELS, averaged over
+    the dispatches that did work, into profiles/fp64_ops.json."""
+    out = {"commands": args.commands, "particles": args.n, "kernels": {}}
+    for key, (frag, src) in FLOP_KERNELS.items():
+        rows = _counter_rows(args.flops_dir, frag)
+        per = {}
+        for (k, c), vs in rows.items():
+            per.setdefault(c, []).extend(vs)
+        need = ["SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                "SQ_INSTS_VALU_TRANS_F64"]
+        if not all(c in per for c in need):
+            continue
+        # dispatches that did work (a gated launch counts next to nothing)
+        tot = [sum(per[c][i] for c in need) for i in range(len(per[need[0]]))]
+        keep = [i for i, t in enumerate(tot) if t > 0.05 * max(tot)]
+        mean = {c: sum(per[c][i] for i in keep) / len(keep) for c in need}
+        flop = 64.0 * (mean[need[0]] + mean[need[1]] + 2.0 * mean[need[2]] + mean[need[3]])
+        out["kernels"][key] = {"kernel": frag, "dispatches": len(keep), "particles": args.n,
+                               "wave_instructions": mean, "flop_per_dispatch": flop,
+                               "src_sha256": src_sha(os.path.join(CSRC, src))}
+    with open(FP64_OPS_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def counters_summary(args):
@@ -358,6 +440,8 @@ def main():
                     help="bracket the force launch of every k-th timed step with hipEvents")
     ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-drift", action="store_true",
+                    help="skip the untimed 1,100-step drift runs (profiler sessions)")
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=2000)
@@ -368,6 +452,8 @@ def main():
                     help="steps per captured hipGraph in the batched form (0: direct launches)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--counters-summary", action="store_true")
+    ap.add_argument("--fp64-ops-summary", action="store_true")
+    ap.add_argument("--flops-dir")
     ap.add_argument("--fetch-dir")
     ap.add_argument("--write-dir")
     ap.add_argument("--copy-fetch-dir")
@@ -381,6 +467,9 @@ def main():
     sys.path.insert(0, ROOT)
     if args.counters_summary:
         counters_summary(args)
+        return
+    if args.fp64_ops_summary:
+        fp64_ops_summary(args)
         return
     import torch
     if not torch.cuda.is_available():
@@ -401,10 +490,10 @@ def main():
         log(f"timing form {f}: {args.steps} steps after {args.warmup} warmup")
         res[f] = run_single(torch, 1 if f == "mixed" else 0, inputs, args.steps, args.warmup,
                             args.profile_every, sample_forces=not args.no_cpu_baseline)
-        res[f]["drift"] = run_drift(1 if f == "mixed" else 0, inputs)
+        res[f]["drift"] = None if args.no_drift else run_drift(1 if f == "mixed" else 0, inputs)
         log(f"  {f}: {res[f]['rate']:.4e} particle-steps/s, {res[f]['ms_per_step']:.4f} ms/step, "
             f"force {res[f]['force_ms_avg']:.4f} ms, nbar {res[f]['nbar']:.2f}, "
-            f"rebuilds {res[f]['rebuilds']}, drift {res[f]['drift']['D']:.3e}")
+            f"rebuilds {res[f]['rebuilds']}, drift {(res[f]['drift'] or {}).get('D')}")
     forms_out = {}
     for f, r in res.items():
         b = force_bytes_per_particle(r["nbar"], f == "mixed")
@@ -421,7 +510,7 @@ def main():
                                 r["nbar"], f == "mixed",
                                 r["rebuilds"] / max(r["steps_total"], 1)) / 1e9 / HBM_PEAK_GBS, 4),
                         "mean_list_length": round(r["nbar"], 3), "rebuilds": r["rebuilds"],
-                        "energy_drift_per_particle_per_1000_steps": r["drift"]["D"],
+                        "energy_drift_per_particle_per_1000_steps": (r["drift"] or {}).get("D"),
                         "energy_drift": r["drift"],
                         "tuned": r["tuned"]}
     if "fp64" in res and "mixed" in res:
@@ -433,7 +522,7 @@ def main():
         log(f"timing the large mixed form: {args.large_steps} steps after 20 warmup")
         rl = run_single(torch, 1, big, args.large_steps, 20, args.profile_every)
         log(f"  large mixed drift window: {DRIFT_STEPS} NVE steps")
-        rl["drift"] = run_drift(1, big)
+        rl["drift"] = None if args.no_drift else run_drift(1, big)
         del big
         bl = force_bytes_per_particle(rl["nbar"], True)
         ach = nl * bl / (max(rl["force_ms_avg"], 1e-12) * 1e-3) / 1e9
@@ -446,14 +535,14 @@ def main():
             "force_ms_avg": round(rl["force_ms_avg"], 4), "force_achieved_gbs": round(ach, 1),
             "force_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
             "mean_list_length": round(rl["nbar"], 3), "rebuilds": rl["rebuilds"],
-            "energy_drift_per_particle_per_1000_steps": rl["drift"]["D"],
+            "energy_drift_per_particle_per_1000_steps": (rl["drift"] or {}).get("D"),
             "energy_drift": rl["drift"], "tuned": rl["tuned"]}
     if "small" in forms:
         log(f"timing the 4000-particle box (FP64): {args.steps} steps, direct and in graphs")
         small = initconf.fcc_system(4000, seed=1, temperature=2.0)
         rd = run_single(torch, 0, small, args.steps, args.warmup, 0)
         rg = run_single(torch, 0, small, args.steps, args.warmup, 0, graph_steps=100)
-        dsmall = run_drift(0, small)
+        dsmall = None if args.no_drift else run_drift(0, small)
         log(f"  small: direct {rd['rate']:.4e}, graphs {rg['rate']:.4e} particle-steps/s")
         forms_out["small_fp64"] = {
             "workload": "lj4000: 4,000-particle binary LJ mixture (FCC n=10, L=14.938, 5 cells "
@@ -462,11 +551,12 @@ def main():
             "value_graphs_100": round(rg["rate"], 1),
             "ms_per_step_graphs_100": round(rg["ms_per_step"], 5),
             "rebuilds": rd["rebuilds"],
-            "energy_drift_per_particle_per_1000_steps": dsmall["D"], "energy_drift": dsmall}
+            "energy_drift_per_particle_per_1000_steps": (dsmall or {}).get("D"),
+            "energy_drift": dsmall}
     if "cells" in forms:
         log(f"timing the list-free cell path (FP64): {args.steps} steps")
         rcell = run_single(torch, 0, inputs, args.steps, args.warmup, args.profile_every, path=3)
-        rcell["drift"] = run_drift(0, inputs, path=3)
+        rcell["drift"] = None if args.no_drift else run_drift(0, inputs, path=3)
         log(f"  cell path: {rcell['rate']:.4e} particle-steps/s, {rcell['ms_per_step']:.4f} ms/step, "
             f"force {rcell['force_ms_avg']:.4f} ms")
         forms_out["cells_fp64"] = {
@@ -474,7 +564,8 @@ def main():
                         "27-cell stencil searched in every force launch)",
             "value": round(rcell["rate"], 1), "ms_per_step": round(rcell["ms_per_step"], 5),
             "force_ms_avg": round(rcell["force_ms_avg"], 5), "rebuilds": rcell["rebuilds"],
-            "energy_drift_per_particle_per_1000_steps": rcell["drift"]["D"],
+            "force_fp64": cells_flops(n, rcell["force_ms_avg"]),
+            "energy_drift_per_particle_per_1000_steps": (rcell["drift"] or {}).get("D"),
             "energy_drift": rcell["drift"]}
         if "fp64" in res:
             forms_out["cells_fp64"]["rate_vs_list_fp64"] = round(rcell["rate"] / res["fp64"]["rate"], 4)
@@ -483,7 +574,8 @@ def main():
         soft_in = initconf.fcc_system(n, seed=6, temperature=0.5)
         rs = run_single(torch, 0, soft_in, args.steps, args.warmup, args.profile_every,
                         potential=1, global_rc=1.2, dt=0.001, T0=0.5)
-        dsoft = run_drift(0, soft_in, potential=1, global_rc=1.2, dt=0.001)
+        dsoft = None if args.no_drift else run_drift(0, soft_in, potential=1, global_rc=1.2,
+                                                     dt=0.001)
         del soft_in
         log(f"  soft sphere: {rs['rate']:.4e} particle-steps/s, {rs['ms_per_step']:.4f} ms/step")
         forms_out["soft_fp64"] = {
@@ -492,9 +584,10 @@ def main():
             "value": round(rs["rate"], 1), "ms_per_step": round(rs["ms_per_step"], 5),
             "force_ms_avg": round(rs["force_ms_avg"], 5),
             "mean_list_length": round(rs["nbar"], 3), "rebuilds": rs["rebuilds"],
-            "nve_energy_drift_per_particle_per_1000_steps": dsoft["D"],
-            "nve_energy_drift": dict(dsoft, note="the same box and start run NVE (the timed "
-                                     "run is canonical, where energy is not conserved)")}
+            "nve_energy_drift_per_particle_per_1000_steps": (dsoft or {}).get("D"),
+            "nve_energy_drift": None if dsoft is None else dict(
+                dsoft, note="the same box and start run NVE (the timed run is canonical, "
+                "where energy is not conserved)")}
     if "batched" in forms:
         log(f"timing batched replicas: {args.replicas} boxes, {args.batched_steps} steps")
         systems, temps = replica_inputs(args.replicas)
@@ -513,9 +606,11 @@ def main():
         forms_out["batched"] = {
             "workload": f"replicas{args.replicas}: sizes log-uniform 1000..65536 "
                         f"({bf['particles']} particles), T0 in [0.4, 2.0], velocity rescale "
-                        f"every step, dt 0.005, skin 0.3, {args.graph_steps}-step hipGraph "
-                        "chunks, force variant autotuned",
+                        f"every step, dt 0.005, {args.graph_steps}-step hipGraph chunks; "
+                        f"path, skin in {list(TUNE_SKINS)} (with it the cell side), tile and "
+                        "force variant autotuned on the batch",
             "tuned_fp64": bf["tuned"], "tuned_mixed": bm["tuned"],
+            "tuner_fp64": bf["tuner"], "tuner_mixed": bm["tuner"],
             "value_fp64": round(bf["rate"], 1), "value_mixed": round(bm["rate"], 1),
             "ms_per_step_fp64": round(bf["ms_per_step"], 5),
             "one_at_a_time_fp64": None if ser is None else round(ser["rate"], 1),

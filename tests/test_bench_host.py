@@ -69,3 +69,21 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_fp64_flops_need_the_current_kernel_source(tmp_path, monkeypatch):
+    src = os.path.join(bench.CSRC, "force_cells.hip")
+    d = {"kernels": {"cells_fp64": {"flop_per_dispatch": 2.0e10, "particles": 1000000,
+                                    "src_sha256": bench.src_sha(src)}}}
+    p = tmp_path / "f.json"
+    p.write_text(json.dumps(d))
+    monkeypatch.setattr(bench, "FP64_OPS_JSON", str(p))
+    assert bench.fp64_flops_per_particle("cells_fp64") == pytest.approx(2.0e4)
+    # 2e4 FLOP per particle x 1e6 particles in 1 ms = 20 TFLOP/s
+    f = bench.cells_flops(1000000, 1.0)
+    assert f["achieved_tflops"] == pytest.approx(20.0)
+    assert f["frac"] == pytest.approx(20.0 / 78.6, rel=1e-3)
+    d["kernels"]["cells_fp64"]["src_sha256"] = "0" * 64
+    p.write_text(json.dumps(d))
+    assert bench.fp64_flops_per_particle("cells_fp64") is None
+    assert bench.cells_flops(1000000, 1.0) is None
