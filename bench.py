@@ -216,7 +216,9 @@ def run_single(torch, precision: int, inputs, steps: int, warmup: int, prof_ever
                   "F_sel": F[sel], "frms": float(np.sqrt(np.mean(np.sum(F * F, axis=1))))}
     sysm.close()
     return {"wall_s": wall, "rate": n * steps / wall, "ms_per_step": 1e3 * wall / steps,
-            "force_ms_avg": prof["force_ms"] / max(prof["force_launches"], 1),
+            # None when no launch was timed (--profile-every 0)
+            "force_ms_avg": (prof["force_ms"] / prof["force_launches"]
+                             if prof["force_launches"] else None),
             "force_launches_timed": prof["force_launches"], "nbar": nbar, "nmax": nmax,
             "rebuilds": obs["n_rebuild"], "steps_total": obs["step"], "sample": sample,
             "tuned": {"tpp": tuned["tpp"], "unroll": tuned["unroll"]}}
@@ -344,7 +346,7 @@ def cells_flops(n: int, force_ms: float):
     FP64 FLOP rate (committed operation counts per particle x n / the
     measured mean launch time) against the 78.6 TFLOP/s FP64 vector peak."""
     fpp = fp64_flops_per_particle("cells_fp64")
-    if fpp is None or force_ms <= 0:
+    if fpp is None or not force_ms:
         return None
     tf = fpp * n / (force_ms * 1e-3) / 1e12
     return {"bound": "fp64 vector alu", "flop_per_particle": round(fpp, 1),
@@ -492,17 +494,23 @@ def main():
                             args.profile_every, sample_forces=not args.no_cpu_baseline)
         res[f]["drift"] = None if args.no_drift else run_drift(1 if f == "mixed" else 0, inputs)
         log(f"  {f}: {res[f]['rate']:.4e} particle-steps/s, {res[f]['ms_per_step']:.4f} ms/step, "
-            f"force {res[f]['force_ms_avg']:.4f} ms, nbar {res[f]['nbar']:.2f}, "
+            f"force {res[f]['force_ms_avg']} ms, nbar {res[f]['nbar']:.2f}, "
             f"rebuilds {res[f]['rebuilds']}, drift {(res[f]['drift'] or {}).get('D')}")
+    def gbs(nb, ms):
+        return None if not ms else nb / (ms * 1e-3) / 1e9
+
+    def rnd(v, k):
+        return None if v is None else round(v, k)
+
     forms_out = {}
     for f, r in res.items():
         b = force_bytes_per_particle(r["nbar"], f == "mixed")
         tr = counters_traffic(f)
+        ach = gbs(n * b, r["force_ms_avg"])
         forms_out[f] = {"value": round(r["rate"], 1), "ms_per_step": round(r["ms_per_step"], 5),
-                        "force_ms_avg": round(r["force_ms_avg"], 5),
-                        "force_achieved_gbs": round(n * b / (max(r["force_ms_avg"], 1e-12) * 1e-3) / 1e9, 1),
-                        "force_frac_hbm": round(n * b / (max(r["force_ms_avg"], 1e-12) * 1e-3) / 1e9
-                                                / HBM_PEAK_GBS, 4),
+                        "force_ms_avg": rnd(r["force_ms_avg"], 5),
+                        "force_achieved_gbs": rnd(ach, 1),
+                        "force_frac_hbm": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
                         "force_traffic_bytes": None if tr is None else round(tr),
                         "force_traffic_over_algorithmic": None if tr is None else round(tr / (n * b), 3),
                         "step_algorithmic_frac_hbm": round(
@@ -525,15 +533,15 @@ def main():
         rl["drift"] = None if args.no_drift else run_drift(1, big)
         del big
         bl = force_bytes_per_particle(rl["nbar"], True)
-        ach = nl * bl / (max(rl["force_ms_avg"], 1e-12) * 1e-3) / 1e9
+        ach = gbs(nl * bl, rl["force_ms_avg"])
         log(f"  large mixed: {rl['rate']:.4e} particle-steps/s, {rl['ms_per_step']:.3f} ms/step, "
-            f"force {rl['force_ms_avg']:.3f} ms")
+            f"force {rl['force_ms_avg']} ms")
         forms_out["large_mixed"] = {
             "workload": f"lj{nl}: {nl}-particle binary LJ mixture, mixed precision, T=2.0 NVE, "
                         "dt 0.005, skin 0.3",
             "value": round(rl["rate"], 1), "ms_per_step": round(rl["ms_per_step"], 4),
-            "force_ms_avg": round(rl["force_ms_avg"], 4), "force_achieved_gbs": round(ach, 1),
-            "force_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+            "force_ms_avg": rnd(rl["force_ms_avg"], 4), "force_achieved_gbs": rnd(ach, 1),
+            "force_frac_hbm": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
             "mean_list_length": round(rl["nbar"], 3), "rebuilds": rl["rebuilds"],
             "energy_drift_per_particle_per_1000_steps": (rl["drift"] or {}).get("D"),
             "energy_drift": rl["drift"], "tuned": rl["tuned"]}
@@ -558,12 +566,12 @@ def main():
         rcell = run_single(torch, 0, inputs, args.steps, args.warmup, args.profile_every, path=3)
         rcell["drift"] = None if args.no_drift else run_drift(0, inputs, path=3)
         log(f"  cell path: {rcell['rate']:.4e} particle-steps/s, {rcell['ms_per_step']:.4f} ms/step, "
-            f"force {rcell['force_ms_avg']:.4f} ms")
+            f"force {rcell['force_ms_avg']} ms")
         forms_out["cells_fp64"] = {
             "workload": f"lj{n} as the headline, list-free cell path (no neighbour list; the "
                         "27-cell stencil searched in every force launch)",
             "value": round(rcell["rate"], 1), "ms_per_step": round(rcell["ms_per_step"], 5),
-            "force_ms_avg": round(rcell["force_ms_avg"], 5), "rebuilds": rcell["rebuilds"],
+            "force_ms_avg": rnd(rcell["force_ms_avg"], 5), "rebuilds": rcell["rebuilds"],
             "force_fp64": cells_flops(n, rcell["force_ms_avg"]),
             "energy_drift_per_particle_per_1000_steps": (rcell["drift"] or {}).get("D"),
             "energy_drift": rcell["drift"]}
@@ -582,7 +590,7 @@ def main():
             "workload": f"soft{n}: binary soft-sphere mixture Eq. (2), rho 1.2, canonical T=0.5 "
                         "(velocity rescale), rc=1.2 for every pair, dt 0.001, skin 0.3, FP64",
             "value": round(rs["rate"], 1), "ms_per_step": round(rs["ms_per_step"], 5),
-            "force_ms_avg": round(rs["force_ms_avg"], 5),
+            "force_ms_avg": rnd(rs["force_ms_avg"], 5),
             "mean_list_length": round(rs["nbar"], 3), "rebuilds": rs["rebuilds"],
             "nve_energy_drift_per_particle_per_1000_steps": (dsoft or {}).get("D"),
             "nve_energy_drift": None if dsoft is None else dict(
@@ -620,9 +628,9 @@ def main():
     head = res.get("fp64") or res.get("mixed")
     head_mixed = "fp64" not in res
     roof = None
-    if head is not None:
+    if head is not None and head["force_ms_avg"]:
         bpp = force_bytes_per_particle(head["nbar"], head_mixed)
-        achieved = n * bpp / (max(head["force_ms_avg"], 1e-12) * 1e-3) / 1e9
+        achieved = gbs(n * bpp, head["force_ms_avg"])
         traffic = counters_traffic("mixed" if head_mixed else "fp64")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
