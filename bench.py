@@ -56,15 +56,16 @@ def force_bytes_per_particle(nbar: float, mixed: bool) -> float:
     """Algorithmic HBM bytes per particle of one in-step force launch of an
     NVE step, which also applies the next step's half kick and drift.
 
-    count (4) + list entries (4 nbar) + the home record (32: x_i and species
-    FP64; mixed: the 16-byte record and the 32-byte FP64 position) + v read
-    and write (48) + x_ref (24) + the drifted position written (32; mixed
-    also its 16-byte record).  The forces stay in registers.  Neighbour
-    positions x_j are gathered from cache and not counted.
+    count (4) + list entries (4 nbar) + the home particle's position and
+    species (24 + 4) + v read and write (48) + x_ref (24) + the drifted
+    position written (24); mixed also reads and writes the 16-byte gather
+    record (32).  The forces stay in registers; neighbour positions x_j are
+    gathered from cache and not counted.  These are the bytes the method
+    moves: the stored position record is 32 bytes (species kept as a
+    double), and its 4 padding bytes per read and 8 per write are not
+    counted.
     """
-    home = 16 + 32 if mixed else 32
-    out = 32 + 16 if mixed else 32
-    return 4 + 4 * nbar + home + 48 + 24 + out
+    return 4 + 4 * nbar + 28 + 48 + 24 + 24 + (32 if mixed else 0)
 
 
 def step_bytes_per_particle(nbar: float, mixed: bool, rebuilds_per_step: float) -> float:

@@ -15,11 +15,13 @@ import bench  # noqa: E402
 
 
 def test_force_bytes_per_particle():
-    # count 4, entries 4 n, home record, v read+write 48, x_ref 24, drifted record(s)
+    # count 4, entries 4 n, home position + species 28, v read+write 48,
+    # x_ref 24, drifted position 24 (mixed: + the 16-byte record read and written)
     n = 92.0
-    assert bench.force_bytes_per_particle(n, False) == pytest.approx(4 + 4 * n + 32 + 48 + 24 + 32)
+    assert bench.force_bytes_per_particle(n, False) == pytest.approx(4 + 4 * n + 28 + 48 + 24 + 24)
+    assert bench.force_bytes_per_particle(n, False) == pytest.approx(128 + 4 * n)
     assert bench.force_bytes_per_particle(n, True) == pytest.approx(
-        4 + 4 * n + (16 + 32) + 48 + 24 + (32 + 16))
+        4 + 4 * n + (16 + 28) + 48 + 24 + (24 + 16))
 
 
 def test_step_bytes_add_the_rebuild_share():
