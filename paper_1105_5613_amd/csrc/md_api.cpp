@@ -248,7 +248,8 @@ md_status sync_and_check(md_ctx c) {
 void run_chain(md_ctx c, hipStream_t s, bool zeroed = false) {
   if (!zeroed) launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
   // several replicas rebuild at different steps: spread each one's blocks
-  const int32_t spread_t = c->nrep > 1 ? 4 : 0, spread_c = c->nrep > 1 ? 8 : 0;
+  // (bin/scatter: groups of 4 tiles; list build: groups of 32 cells)
+  const int32_t spread_t = c->nrep > 1 ? 4 : 0, spread_c = c->nrep > 1 ? 32 : 0;
   launch_bin(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->pos, c->id, c->img, c->counts,
              c->cell_of, c->slot, c->st, spread_t);
   launch_scan(s, c->ncells, c->counts, c->cell_start, c->bsum, c->st);

@@ -217,7 +217,8 @@ inline int32_t fma_pair_form(const double* t, int32_t ntypes) {
   }
   return 2;
 }
-// nlist.hip.  thr_form: fma_pair_form of the list thresholds.
+// nlist.hip.  thr_form: fma_pair_form of the list thresholds.  spread: 0, or
+// the number of consecutive cells whose blocks share an XCD (see xcd_spread).
 void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDesc* reps,
                   const int32_t* rebuild, const PairTab* tab, int32_t thr_form,
                   const int32_t* cell_start, int32_t stride, int32_t cap,

@@ -106,62 +106,55 @@ __global__ __launch_bounds__(kTile) void k_nlist(
 }
 
 
-// One wave per home cell (nc >= 3).  The candidates of the cell -- the 9
-// neighbour rows, each one to three contiguous particle ranges with their
-// periodic shift -- are packed 64 to a chunk, one candidate per lane, with
-// x_j + s L formed once per chunk.  For every home particle (uniform loop,
-// coordinates through scalar loads) each lane tests its candidate; the hits
-// are compacted with a ballot and appended to the home particle's row in
-// candidate order.  Copying the new order into the live arrays is done here
-// as well.
-constexpr int kCwGroup = 64;  // home particles per pass: lane h keeps the count of home h
-constexpr int kCwHomes = 4;   // home particles tested per iteration
-constexpr int kCwBuf = 1024;  // list entries staged in LDS per wave (4 KB)
+// One wave per home cell (nc >= 3), in two phases per group of at most
+// kCwGroup home particles.
+//
+// Test phase: the candidates of the cell -- the 9 neighbour rows, each one to
+// three contiguous particle ranges with their periodic shift -- are packed 64
+// to a chunk, one candidate per lane, with x_j + s L formed once per chunk.
+// For every home particle (wave-uniform loop, coordinates through scalar
+// loads) each lane tests its candidate.  The ballot of the hits is the whole
+// result: its two 32-bit words go to lane h of two registers (one
+// v_writelane each) and, once per chunk, to LDS beside the chunk's list
+// entries.  Nothing is done per hit.
+//
+// Write phase: lane h walks the set bits of home h's words in candidate
+// order, the t-th bit giving the home's t-th list entry.  The lanes go in
+// lock step, so iteration t stores entry t of every home of the group: row t
+// of the sliced list, a contiguous segment for the group's consecutive
+// particles, written whole in one store.
+//
+// A neighbourhood of more than kCwChunks * 64 candidates is taken in passes;
+// the rows of a later pass start at each home's running count (the stores of
+// such a pass are scattered; correct, and rare at the cell sizes used).
+// Copying the new order into the live arrays is done here as well.
+constexpr int kCwGroup = 32;   // home particles per group (lanes of the write phase)
+constexpr int kCwHomes = 4;    // home particles tested per iteration
+constexpr int kCwChunks = 12;  // candidate chunks per pass (768 candidates, 6 KB of LDS)
+constexpr int kCwWaves = 1;    // waves (cells) per block: a finished cell frees its LDS
+                               // at once instead of waiting for the block's slowest cell
 constexpr double kFar = 1.0e300;  // x of the idle lanes of a chunk: r^2 overflows to +inf
+static_assert(kCwGroup == 32, "the write phase gives each home two lanes of the wave");
 
-// Append the hits of the lane's candidate for home particle hl of the group
-// (wave-uniform) at that particle's running count cnt.  Rows below rows_lds
-// go to the wave's LDS buffer ([home][row] layout: a wave-uniform base plus
-// the row, one full-rate address operation; rows_lds is odd, so the row
-// write-out, whose lanes read one row of consecutive homes, is free of bank
-// conflicts) and reach the list later as whole row segments; rows above it
-// are stored straight into the home particle's list row hrow (a wave-uniform
-// pointer: one scalar base plus a 32-bit lane offset per store).
-template <typename E>
-__device__ inline int32_t cw_append(uint64_t mask, bool hit, int32_t cnt, int32_t hl,
-                                    uint32_t entry, int32_t cap, int32_t rows_lds,
-                                    uint32_t* buf, E* __restrict__ hrow) {
-  if (mask) {
-    const int32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-    const int32_t k = cnt + rk;
-    if (hit && k < cap) {
-      if (k < rows_lds)
-        buf[hl * rows_lds + k] = entry;
-      else
-        *reinterpret_cast<E*>(reinterpret_cast<char*>(hrow) +
-                              (uint32_t)k * (uint32_t)(kSlice * sizeof(E))) = (E)entry;
-    }
-    cnt += (int32_t)__popcll(mask);
-  }
-  return cnt;
+// lo[l] = low word of m, hi[l] = high word, for the wave-uniform lane l: two
+// v_writelane with the lane in M0 (the clang in use has no builtin for it,
+// and a lane select in another scalar register would break the one-scalar
+// operand limit).  Lanes other than l keep their values.  m is usually the
+// scalar result of the vector compare just before; the compiler inserts no
+// wait states inside inline asm, so the block starts with the longest one a
+// lane operation needs after a vector write of a scalar register it reads.
+__device__ inline void write_lanes(uint32_t& lo, uint32_t& hi, uint64_t m, int32_t l) {
+  asm volatile("s_nop 4\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
+               : "+v"(lo), "+v"(hi)
+               : "s"((uint32_t)m), "s"((uint32_t)(m >> 32)), "{m0}"(l));
 }
 
-// v[l] = x for the wave-uniform lane l (one v_writelane; the clang in use
-// has no builtin for it).  Lanes other than l keep their value.
-__device__ inline int32_t write_lane(int32_t v, int32_t x, int32_t l) {
-  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "{m0}"(l));
-  return v;
-}
-
-// List row of home particle gbase + h, from the row of gbase: a group of at
-// most 64 consecutive particles spans at most two slices.
-template <typename E>
-__device__ inline E* home_row(E* grow, int32_t gbase, int32_t h, int32_t cap) {
-  const uint32_t off = (uint32_t)h + (((gbase & (kSlice - 1)) + h) >= kSlice
-                                          ? (uint32_t)(cap - 1) * (uint32_t)kSlice
-                                          : 0u);
-  return grow + __builtin_amdgcn_readfirstlane(off);
+// LDS written by some lanes of the wave and read by others: order the
+// accesses (the LDS unit serves one wave's operations in issue order).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Cut-off threshold of the pair (home species a, lane's candidate species b),
@@ -182,22 +175,13 @@ __device__ inline double pick_thr(double wa, double t0, double d, double t1, dou
   }
 }
 
-// One wave per home cell (nc >= 3): the lanes take the 64 candidates of one
-// chunk of the cell's packed 27-cell neighbourhood, and the wave walks the
-// home particles (kCwHomes per iteration, positions in scalar registers);
-// hits are compacted with a ballot.  The first kCwBuf / (homes) rows of the
-// cell's lists are assembled in LDS and written out row by row (one
-// contiguous store per row instead of scattered single entries); the LDS
-// buffer is kept small because occupancy matters more here than write
-// combining.
-//
 // TILE = false: entries are sorted index | image code (uint32, gather path).
 // TILE = true: entries are the partner's LDS slot in the staged neighbourhood
 // of the row tile holding the home cell (stage.h) | species << 14 (uint16,
 // staged path); the slot of a candidate is its piece's first slot in that
 // layout plus its offset inside the piece.
-template <int HPI, int BUF, bool TILE, int NT>
-__global__ __launch_bounds__(256) void k_nlist_cells(
+template <int HPI, bool TILE, int NT>
+__global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
     int32_t ncells, const int32_t* __restrict__ cell_rep, const RepDesc* __restrict__ reps,
     const int32_t* __restrict__ rebuild, const PairTab* __restrict__ tab,
     const int32_t* __restrict__ cell_start, int32_t stride, int32_t cap,
@@ -210,18 +194,20 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
     int32_t spread) {
   using E = typename std::conditional<TILE, uint16_t, uint32_t>::type;
   __shared__ double s_thr[16];
-  __shared__ int32_t s_pre[4][28];    // first packed candidate of piece p
-  __shared__ int32_t s_k0[4][27];     // first sorted index of piece p
-  __shared__ int32_t s_code[4][27];   // image code of piece p (shift -1/0/1 per axis)
-  __shared__ int32_t s_l0[4][27];     // TILE: first LDS slot of piece p in the tile layout
-  __shared__ int32_t s_rowsz[4][9];   // TILE: slots of tile row q
-  extern __shared__ uint32_t s_list[];  // [4][kCwBuf]
+  __shared__ int32_t s_pre[kCwWaves][28];    // first packed candidate of piece p
+  __shared__ int32_t s_k0[kCwWaves][27];     // first sorted index of piece p
+  __shared__ int32_t s_code[kCwWaves][27];   // image code of piece p (shift -1/0/1 per axis)
+  __shared__ int32_t s_l0[kCwWaves][27];     // TILE: first LDS slot of piece p in the tile layout
+  __shared__ int32_t s_rowsz[kCwWaves][9];   // TILE: slots of tile row q
+  __shared__ uint32_t s_ent[kCwWaves][kCwChunks * 64];              // entry of each candidate
+  __shared__ uint32_t s_hits[kCwWaves][2 * kCwChunks * kCwGroup];   // [word][home] hit bits
   if (!st->any_rebuild) return;  // whole block: one flag load when nothing rebuilds
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is wave-uniform; as a scalar, the per-cell values below are too
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int32_t c =
-      (spread ? xcd_spread(blockIdx.x, spread) : xcd_block(blockIdx.x, gridDim.x)) * 4 + w;
+      (spread ? xcd_spread(blockIdx.x, spread) : xcd_block(blockIdx.x, gridDim.x)) * kCwWaves + w;
   if (c >= ncells) return;
   const int32_t r = cell_rep[c];
   if (!rebuild[r]) return;
@@ -231,7 +217,8 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   const int32_t lc = c - R.coff;
   const int32_t qx = lc % nc, qy = (lc / nc) % nc, qz = lc / (nc * nc);
   const int32_t h0 = cell_start[c], nh = cell_start[c + 1] - h0;
-  uint32_t* buf = s_list + w * BUF;
+  uint32_t* const ent = s_ent[w];
+  uint32_t* const hits = s_hits[w];
 
   // pieces: lane q < 9 builds neighbour row q (dz = q/3 - 1, dy = q%3 - 1)
   if (lane < 9) {
@@ -290,115 +277,159 @@ __global__ __launch_bounds__(256) void k_nlist_cells(
   __builtin_amdgcn_wave_barrier();
   const int32_t ncand = s_pre[w][27];
 
-  for (int32_t g0 = 0; g0 < nh; g0 += kCwGroup) {
-    const int32_t gn = nh - g0 < kCwGroup ? nh - g0 : kCwGroup;
+  // groups of at most kCwGroup home particles, of equal size
+  const int32_t ngrp = (nh + kCwGroup - 1) / kCwGroup;
+  const int32_t gsz = ngrp ? (nh + ngrp - 1) / ngrp : 1;
+  // first packed candidate of the cell's own particles (the main piece of the
+  // central row, the only candidates that can be a home particle itself)
+  const int32_t sv0 = s_pre[w][13] + (h0 - s_k0[w][13]);
+  for (int32_t g0 = 0; g0 < nh; g0 += gsz) {
+    const int32_t gn = nh - g0 < gsz ? nh - g0 : gsz;
     const int32_t gbase = __builtin_amdgcn_readfirstlane(h0 + g0);  // wave-uniform
-    const int32_t rows_lds = (BUF / gn - 1) | 1;  // odd, <= BUF / gn
     E* const grow = nbr + list_base(gbase, cap);
-    int32_t cntv = 0;  // lane h: neighbours found so far for home gbase + h
-    for (int32_t base = 0; base < ncand; base += 64) {
-      const int32_t v = base + lane;
-      const bool valid = v < ncand;
-      // piece of candidate v: the last p with s_pre[p] <= v
-      int p = 0;
+    const int32_t gs0 = sv0 + g0;  // packed candidates of the group's own particles: [gs0, gs0 + gn)
+    int32_t cntv = 0;              // lane h: hits of home gbase + h so far
+    for (int32_t pb = 0; pb < ncand; pb += kCwChunks * 64) {
+      const int32_t pend = ncand - pb < kCwChunks * 64 ? ncand : pb + kCwChunks * 64;
+      const int32_t nwords = 2 * ((pend - pb + 63) >> 6);
+      int32_t passv = 0;  // lane h: hits of home gbase + h in this pass
+      // ---- test phase ----
+      for (int32_t base = pb; base < pend; base += 64) {
+        const int32_t ci = (base - pb) >> 6;
+        const int32_t v = base + lane;
+        const bool valid = v < ncand;
+        // piece of candidate v: the last p with s_pre[p] <= v
+        int p = 0;
 #pragma unroll
-      for (int step = 16; step >= 1; step >>= 1)
-        if (p + step <= 26 && s_pre[w][p + step] <= v) p += step;
-      const int32_t k = valid ? s_k0[w][p] + (v - s_pre[w][p]) : h0;
-      const uint32_t code = (uint32_t)s_code[w][p];
-      const double4 q = pos_tmp[k];
-      // the periodic shift of the piece: x_j + s L; lanes past the last
-      // candidate sit far away, so their test fails without a mask
-      const double sx = (double)(((int32_t)(code << 4)) >> 30) * R.L;
-      const double sy = (double)(((int32_t)(code << 2)) >> 30) * R.L;
-      const double sz = (double)(((int32_t)code) >> 30) * R.L;
-      const double xs = valid ? q.x + sx : kFar, ys = q.y + sy, zs = q.z + sz;
-      const int32_t tj = (int32_t)q.w;  // thr[4 ta + tj] is the pair (ta, tj)
-      const double t0 = s_thr[tj], t1 = s_thr[4 + tj], t2 = s_thr[8 + tj], t3 = s_thr[12 + tj];
-      const double d01 = t1 - t0;
-      uint32_t entry;
-      if constexpr (TILE) {
-        entry = (uint32_t)((s_l0[w][p] + (v - s_pre[w][p])) & 0x3fff) | ((uint32_t)tj << 14);
-      } else if (dcode) {
-        // d = c_i - c_j - s nc: -dy, -dz of the row; along x from the
-        // partner's build-time cell and the piece's shift
-        const int32_t row = p / 3, kind = p - 3 * row;
-        const int32_t cxj = cell_coord(q.x, R.inv_cell, nc);
-        entry = (uint32_t)k | image_code(qx - cxj - (kind - 1) * nc, 1 - row % 3, 1 - row / 3);
-      } else {
-        entry = (uint32_t)k | code;
-      }
-      // the cell's own particles -- the only candidates that can be the home
-      // particle itself -- are the main piece of the central row; chunks that
-      // miss them skip the self test
-      const int32_t sv0 = s_pre[w][13] + (h0 - s_k0[w][13]);
-      const bool self_chunk = base < sv0 + nh && sv0 < base + 64;
-      int32_t h = 0;
-      // HPI home particles per iteration (wave-uniform, scalar loads): the
-      // distances first (independent work), then test, ballot and append
-      // home by home
-      auto homes = [&](auto self_tag) {
-        constexpr bool SELF = decltype(self_tag)::value;
-        for (; h + HPI <= gn; h += HPI) {
-          const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
-          double ra[HPI], tha[HPI];
-#pragma unroll
-          for (int u = 0; u < HPI; ++u) {
-            const double4 pa = pos_tmp[i0 + u];
-            const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
-            ra[u] = (ax * ax + ay * ay) + az * az;
-            tha[u] = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
-          }
-#pragma unroll
-          for (int u = 0; u < HPI; ++u) {
-            const bool hit = SELF ? (k != i0 + u && ra[u] < tha[u]) : ra[u] < tha[u];
-            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-            int32_t cu = __builtin_amdgcn_readlane(cntv, h + u);
-            cu = cw_append(m, hit, cu, h + u, entry, cap, rows_lds, buf,
-                           home_row(grow, gbase, h + u, cap));
-            cntv = write_lane(cntv, cu, h + u);
-          }
+        for (int step = 16; step >= 1; step >>= 1)
+          if (p + step <= 26 && s_pre[w][p + step] <= v) p += step;
+        const int32_t k = valid ? s_k0[w][p] + (v - s_pre[w][p]) : h0;
+        const uint32_t code = (uint32_t)s_code[w][p];
+        const double4 q = pos_tmp[k];
+        // the periodic shift of the piece: x_j + s L; lanes past the last
+        // candidate sit far away, so their test fails without a mask
+        const double sx = (double)(((int32_t)(code << 4)) >> 30) * R.L;
+        const double sy = (double)(((int32_t)(code << 2)) >> 30) * R.L;
+        const double sz = (double)(((int32_t)code) >> 30) * R.L;
+        const double xs = valid ? q.x + sx : kFar, ys = q.y + sy, zs = q.z + sz;
+        const int32_t tj = (int32_t)q.w;  // thr[4 ta + tj] is the pair (ta, tj)
+        const double t0 = s_thr[tj], t1 = s_thr[4 + tj], t2 = s_thr[8 + tj], t3 = s_thr[12 + tj];
+        const double d01 = t1 - t0;
+        uint32_t entry;
+        if constexpr (TILE) {
+          entry = (uint32_t)((s_l0[w][p] + (v - s_pre[w][p])) & 0x3fff) | ((uint32_t)tj << 14);
+        } else if (dcode) {
+          // d = c_i - c_j - s nc: -dy, -dz of the row; along x from the
+          // partner's build-time cell and the piece's shift
+          const int32_t row = p / 3, kind = p - 3 * row;
+          const int32_t cxj = cell_coord(q.x, R.inv_cell, nc);
+          entry = (uint32_t)k | image_code(qx - cxj - (kind - 1) * nc, 1 - row % 3, 1 - row / 3);
+        } else {
+          entry = (uint32_t)k | code;
         }
-      };
-      if (self_chunk)
-        homes(std::true_type{});
-      else
-        homes(std::false_type{});
-      for (; h < gn; ++h) {
-        const int32_t ia = __builtin_amdgcn_readfirstlane(gbase + h);
-        const double4 pa = pos_tmp[ia];
-        const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
-        const double ra = (ax * ax + ay * ay) + az * az;
-        const double tha = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
-        const bool hita = k != ia && ra < tha;
-        const uint64_t ma = __builtin_amdgcn_ballot_w64(hita);
-        int32_t ca = __builtin_amdgcn_readlane(cntv, h);
-        ca = cw_append(ma, hita, ca, h, entry, cap, rows_lds, buf, home_row(grow, gbase, h, cap));
-        cntv = write_lane(cntv, ca, h);
+        ent[ci * 64 + lane] = entry;
+        // chunks that miss the group's own particles skip the self test
+        const bool self_chunk = base < gs0 + gn && gs0 < base + 64;
+        uint32_t mlo = 0, mhi = 0;  // lane h: hit bits of home gbase + h
+        int32_t h = 0;
+        // HPI home particles per iteration (wave-uniform, scalar loads): the
+        // distances first (independent work), then the ballots
+        auto homes = [&](auto self_tag) {
+          constexpr bool SELF = decltype(self_tag)::value;
+          for (; h + HPI <= gn; h += HPI) {
+            const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
+            double ra[HPI], tha[HPI];
+#pragma unroll
+            for (int u = 0; u < HPI; ++u) {
+              const double4 pa = pos_tmp[i0 + u];
+              const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
+              ra[u] = (ax * ax + ay * ay) + az * az;
+              tha[u] = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
+            }
+#pragma unroll
+            for (int u = 0; u < HPI; ++u) {
+              const bool hit = SELF ? ((k != i0 + u) & (ra[u] < tha[u])) : ra[u] < tha[u];
+              write_lanes(mlo, mhi, __builtin_amdgcn_ballot_w64(hit), h + u);
+            }
+          }
+        };
+        if (self_chunk)
+          homes(std::true_type{});
+        else
+          homes(std::false_type{});
+        for (; h < gn; ++h) {
+          const int32_t ia = __builtin_amdgcn_readfirstlane(gbase + h);
+          const double4 pa = pos_tmp[ia];
+          const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
+          const double ra = (ax * ax + ay * ay) + az * az;
+          const double tha = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
+          write_lanes(mlo, mhi, __builtin_amdgcn_ballot_w64((k != ia) & (ra < tha)), h);
+        }
+        if (lane < kCwGroup) {
+          hits[(2 * ci) * kCwGroup + lane] = mlo;
+          hits[(2 * ci + 1) * kCwGroup + lane] = mhi;
+        }
+        passv += (int32_t)(__popc(mlo) + __popc(mhi));  // 0 on lanes >= gn
       }
+      wave_lds_sync();
+      // ---- write phase ----
+      // home h = lane & 31 stores its first lim rows of the pass, from row
+      // cntv on: lane h the first S of them, lane h + 32 the rest (S = half
+      // the longest), each lane walking the home's hit bits from its first
+      // rank on.  Both halves store whole row segments.
+      const int32_t room = cap - cntv > 0 ? cap - cntv : 0;
+      const int32_t lim = lane < gn ? (passv < room ? passv : room) : 0;
+      int32_t mxl = lim;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) mxl = max(mxl, __shfl_xor(mxl, d, 64));
+      const int32_t half = (__builtin_amdgcn_readfirstlane(mxl) + 1) >> 1;
+      const int32_t hl = lane & (kCwGroup - 1), seg = lane >> 5;
+      const int32_t lim_h = __shfl(lim, hl, 64), cnt_h = __shfl(cntv, hl, 64);
+      const int32_t rbeg = seg ? half : 0;
+      const int32_t nseg = (seg ? lim_h : (lim_h < half ? lim_h : half)) - rbeg;
+      int32_t wi = 0;
+      uint32_t cur = 0u;
+      if (nseg > 0) {
+        cur = hits[hl];
+        if (seg) {
+          // the word holding the home's hit of rank rbeg, then that bit
+          int32_t acc = 0, pc = __popc(cur);
+          while (acc + pc <= rbeg && wi + 1 < nwords) {
+            acc += pc;
+            ++wi;
+            cur = hits[wi * kCwGroup + hl];
+            pc = __popc(cur);
+          }
+          for (int32_t j = acc; j < rbeg; ++j) cur &= cur - 1u;
+        }
+      }
+      // list slot of home gbase + hl relative to grow (a group of at most 32
+      // consecutive particles spans at most two slices)
+      const uint32_t hslot =
+          (uint32_t)hl +
+          (((gbase & (kSlice - 1)) + hl) >= kSlice ? (uint32_t)(cap - 1) * (uint32_t)kSlice : 0u);
+      const uint32_t loff = hslot + (uint32_t)(cnt_h + rbeg) * (uint32_t)kSlice;
+      for (int32_t t = 0; t < half; ++t) {
+        if (t < nseg) {
+          // the next set bit; t < nseg leaves one in words wi.. (the bound
+          // on wi only keeps every read inside the pass's words)
+          while (cur == 0u && wi + 1 < nwords) {
+            ++wi;
+            cur = hits[wi * kCwGroup + hl];
+          }
+          const uint32_t b = (uint32_t)__builtin_ctz(cur | 0x80000000u);
+          cur &= cur - 1u;
+          E* const rowt = grow + (size_t)t * kSlice;  // wave-uniform
+          rowt[loff] = (E)ent[wi * 32 + (int32_t)b];
+        }
+      }
+      cntv += passv;
+      wave_lds_sync();  // the next pass or group rewrites ent and hits
     }
     if (lane < gn) {
       ncount[gbase + lane] = cntv;
       if (cntv > cap) atomicOr(&st->err, kErrOverflow);
     }
-    if (BUF == 0) continue;
-    // write the staged rows: row k of the group is gn consecutive entries
-    int32_t mx = lane < gn ? cntv : 0;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d, 64));
-    const int32_t rows = min(min(mx, cap), rows_lds);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int32_t per = 64 / gn;  // rows per store
-    const int32_t lr = lane / gn, lh = lane - lr * gn;
-    if (lr < per)
-      for (int32_t kk = lr; kk < rows; kk += per)
-        nbr[list_base(gbase + lh, cap) + (size_t)kk * kSlice] = (E)buf[lh * rows_lds + kk];
-    // the next group reuses the buffer
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   // the new cell order becomes the live state
   for (int32_t h = lane; h < nh; h += 64) {
@@ -429,12 +460,12 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
   // mixed lists (records present) carry cell offsets instead of images
   const int32_t dcode = pos16 != nullptr;
   if (any_multi) {
-    const int32_t nb = (ncells + 3) / 4, grid = spread ? spread_grid(nb, spread) : nb;
+    const int32_t nb = (ncells + kCwWaves - 1) / kCwWaves;
+    const int32_t g = spread / kCwWaves, grid = g ? spread_grid(nb, g) : nb;
 #define KN(NT)                                                                             \
-  k_nlist_cells<kCwHomes, kCwBuf, false, NT>                                               \
-      <<<grid, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                                   \
+  k_nlist_cells<kCwHomes, false, NT><<<grid, 64 * kCwWaves, 0, s>>>(                       \
           ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, \
-          id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr, dcode, spread)
+          id_tmp, pos, vel, id, xref, nbr, ncount, st, pos16, nullptr, nullptr, dcode, g)
     if (thr_form == 2) KN(2); else KN(4);
 #undef KN
   }
@@ -450,12 +481,12 @@ void launch_nlist_tiles(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         double4* pos, double* vel, int32_t* id, double* xref, uint16_t* nbr16,
                         int32_t* ncount, DevState* st, const int32_t* cell_tile,
                         const RowTile* rtiles, int32_t spread) {
-  const int32_t nb = (ncells + 3) / 4, grid = spread ? spread_grid(nb, spread) : nb;
+  const int32_t nb = (ncells + kCwWaves - 1) / kCwWaves;
+  const int32_t g = spread / kCwWaves, grid = g ? spread_grid(nb, g) : nb;
 #define KT(NT)                                                                                   \
-  k_nlist_cells<kCwHomes, kCwBuf, true, NT>                                                      \
-      <<<grid, 256, 4 * kCwBuf * sizeof(uint32_t), s>>>(                                         \
+  k_nlist_cells<kCwHomes, true, NT><<<grid, 64 * kCwWaves, 0, s>>>(                              \
           ncells, cell_rep, reps, rebuild, tab, cell_start, stride, cap, pos_tmp, vel_tmp, id_tmp, \
-          pos, vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles, 0, spread)
+          pos, vel, id, xref, nbr16, ncount, st, nullptr, cell_tile, rtiles, 0, g)
   if (thr_form == 2) KT(2); else KT(4);
 #undef KT
 }
