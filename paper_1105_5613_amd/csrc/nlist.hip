@@ -131,8 +131,9 @@ __global__ __launch_bounds__(kTile) void k_nlist(
 constexpr int kCwGroup = 32;   // home particles per group (lanes of the write phase)
 constexpr int kCwHomes = 4;    // home particles tested per iteration
 constexpr int kCwChunks = 12;  // candidate chunks per pass (768 candidates, 6 KB of LDS)
-constexpr int kCwWaves = 1;    // waves (cells) per block: a finished cell frees its LDS
-                               // at once instead of waiting for the block's slowest cell
+constexpr int kCwWaves = 4;    // waves (cells) per block: a launch with nothing to rebuild
+                               // costs its block count; one or two cells per block measured
+                               // slower both idle and building
 constexpr double kFar = 1.0e300;  // x of the idle lanes of a chunk: r^2 overflows to +inf
 static_assert(kCwGroup == 32, "the write phase gives each home two lanes of the wave");
 
