@@ -136,6 +136,8 @@ constexpr int kCwWaves = 4;    // waves (cells) per block: a launch with nothing
                                // slower both idle and building
 constexpr double kFar = 1.0e300;  // x of the idle lanes of a chunk: r^2 overflows to +inf
 static_assert(kCwGroup == 32, "the write phase gives each home two lanes of the wave");
+static_assert(kCwHomes == 3 || kCwHomes == 4,
+              "the home loop leaves at most one block of 2 and one of 1");
 
 // lo[l] = low word of m, hi[l] = high word, for the wave-uniform lane l: two
 // v_writelane with the lane in M0 (the clang in use has no builtin for it,
@@ -333,39 +335,37 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
         const bool self_chunk = base < gs0 + gn && gs0 < base + 64;
         uint32_t mlo = 0, mhi = 0;  // lane h: hit bits of home gbase + h
         int32_t h = 0;
-        // HPI home particles per iteration (wave-uniform, scalar loads): the
-        // distances first (independent work), then the ballots
-        auto homes = [&](auto self_tag) {
+        // U home particles (wave-uniform, scalar loads): the distances
+        // first (independent work), then the ballots; blocks of HPI, then
+        // one of 2 and one of 1 for the rest, all with the same code
+        auto block = [&](auto self_tag, auto u_tag) {
           constexpr bool SELF = decltype(self_tag)::value;
-          for (; h + HPI <= gn; h += HPI) {
-            const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
-            double ra[HPI], tha[HPI];
+          constexpr int U = decltype(u_tag)::value;
+          const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
+          double ra[U], tha[U];
 #pragma unroll
-            for (int u = 0; u < HPI; ++u) {
-              const double4 pa = pos_tmp[i0 + u];
-              const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
-              ra[u] = (ax * ax + ay * ay) + az * az;
-              tha[u] = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
-            }
-#pragma unroll
-            for (int u = 0; u < HPI; ++u) {
-              const bool hit = SELF ? ((k != i0 + u) & (ra[u] < tha[u])) : ra[u] < tha[u];
-              write_lanes(mlo, mhi, __builtin_amdgcn_ballot_w64(hit), h + u);
-            }
+          for (int u = 0; u < U; ++u) {
+            const double4 pa = pos_tmp[i0 + u];
+            const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
+            ra[u] = (ax * ax + ay * ay) + az * az;
+            tha[u] = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
           }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const bool hit = SELF ? ((k != i0 + u) & (ra[u] < tha[u])) : ra[u] < tha[u];
+            write_lanes(mlo, mhi, __builtin_amdgcn_ballot_w64(hit), h + u);
+          }
+          h += U;
+        };
+        auto homes = [&](auto self_tag) {
+          while (h + HPI <= gn) block(self_tag, std::integral_constant<int, HPI>{});
+          if (h + 2 <= gn) block(self_tag, std::integral_constant<int, 2>{});
+          if (h < gn) block(self_tag, std::integral_constant<int, 1>{});
         };
         if (self_chunk)
           homes(std::true_type{});
         else
           homes(std::false_type{});
-        for (; h < gn; ++h) {
-          const int32_t ia = __builtin_amdgcn_readfirstlane(gbase + h);
-          const double4 pa = pos_tmp[ia];
-          const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
-          const double ra = (ax * ax + ay * ay) + az * az;
-          const double tha = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
-          write_lanes(mlo, mhi, __builtin_amdgcn_ballot_w64((k != ia) & (ra < tha)), h);
-        }
         if (lane < kCwGroup) {
           hits[(2 * ci) * kCwGroup + lane] = mlo;
           hits[(2 * ci + 1) * kCwGroup + lane] = mhi;
@@ -410,13 +410,22 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
           (uint32_t)hl +
           (((gbase & (kSlice - 1)) + hl) >= kSlice ? (uint32_t)(cap - 1) * (uint32_t)kSlice : 0u);
       const uint32_t loff = hslot + (uint32_t)(cnt_h + rbeg) * (uint32_t)kSlice;
+      // the word after the current one, read ahead: a lane whose word is used
+      // up (some lane nearly every iteration) takes it without waiting
+      uint32_t nxt = (nseg > 0 && wi + 1 < nwords) ? hits[(wi + 1) * kCwGroup + hl] : 0u;
       for (int32_t t = 0; t < half; ++t) {
         if (t < nseg) {
           // the next set bit; t < nseg leaves one in words wi.. (the bound
           // on wi only keeps every read inside the pass's words)
-          while (cur == 0u && wi + 1 < nwords) {
+          if (cur == 0u && wi + 1 < nwords) {
             ++wi;
-            cur = hits[wi * kCwGroup + hl];
+            cur = nxt;
+            nxt = wi + 1 < nwords ? hits[(wi + 1) * kCwGroup + hl] : 0u;
+            while (cur == 0u && wi + 1 < nwords) {  // an empty word: rare
+              ++wi;
+              cur = nxt;
+              nxt = wi + 1 < nwords ? hits[(wi + 1) * kCwGroup + hl] : 0u;
+            }
           }
           const uint32_t b = (uint32_t)__builtin_ctz(cur | 0x80000000u);
           cur &= cur - 1u;
