@@ -43,7 +43,7 @@ CSRC = os.path.join(ROOT, "paper_1105_5613_amd", "csrc")
 # kernels whose FP64 operation counts the bench turns into FLOP/s: name
 # fragment in the counter output -> source file
 FLOP_KERNELS = {"cells_fp64": ("k_force_cells<false", "force_cells.hip"),
-                "nlist_fp64": ("k_nlist_cells<4, 1024, false", "nlist.hip"),
+                "nlist_fp64": ("k_nlist_cells<4, false", "nlist.hip"),
                 "force_fp64": ("k_force<false, 2", "force.hip")}
 COPY_BYTES = 1 << 30
 
