@@ -56,6 +56,17 @@ __device__ inline void load_pair(PairLds<T>& s, const PairTab* __restrict__ tab)
   }
 }
 
+// Mixed form: one 64-byte LDS record per species pair, so the cut-off test
+// and the pair constants take one address computation (ab << 6).
+struct alignas(16) PairRec {
+  float sig2, f12, f6, fs;  // force
+  double rc2;               // the FP64 cut-off test
+  double pad;
+  float c12, c6, vc, rc;    // energy
+  float pad2[4];
+};
+static_assert(sizeof(PairRec) == 64, "PairRec is addressed as ab << 6");
+
 __device__ inline int32_t decode_shift(uint32_t e, int lsb) {
   // two-bit two's-complement field at bit lsb of e
   return ((int32_t)(e << (30 - lsb))) >> 30;
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(kTile) void k_force(
   __shared__ PairLds<T> P;
   __shared__ double s_mass[4], s_im[4];
   __shared__ double4 s_doff[64];  // mixed: d * cell side for each entry code
-  __shared__ double s_rc2[16];    // mixed: cut-offs for the FP64 test
+  __shared__ PairRec s_pr[16];    // mixed: the pair constants, one record per pair
   if (halted(st)) {
     // a list build queued before this launch overflowed (see kHalt): the
     // step is not taken; the later queued rebuild chains are switched off,
@@ -196,7 +207,22 @@ __global__ __launch_bounds__(kTile) void k_force(
     s_doff[threadIdx.x] = make_double4((double)decode_shift(c, 26) * sd,
                                        (double)decode_shift(c, 28) * sd,
                                        (double)decode_shift(c, 30) * sd, 0.0);
-    if (threadIdx.x < 16) s_rc2[threadIdx.x] = tab->rc2[threadIdx.x];
+    if (threadIdx.x < 16) {
+      const int k = threadIdx.x;
+      PairRec r;
+      r.sig2 = (float)tab->sig2[k];
+      r.f12 = (float)tab->f12[k];
+      r.f6 = (float)tab->f6[k];
+      r.fs = (float)tab->fs[k];
+      r.rc2 = tab->rc2[k];
+      r.pad = 0.0;
+      r.c12 = (float)tab->c12[k];
+      r.c6 = (float)tab->c6[k];
+      r.vc = (float)tab->vc[k];
+      r.rc = (float)tab->rc[k];
+      r.pad2[0] = r.pad2[1] = r.pad2[2] = r.pad2[3] = 0.0f;
+      s_pr[k] = r;
+    }
   }
   __syncthreads();
   const double L = Rp.L;
@@ -248,21 +274,24 @@ __global__ __launch_bounds__(kTile) void k_force(
                        ez = __builtin_fma((double)(pi.z - q[u].z), qinv, dd.z);
           const int32_t ab = ti * 4 + (int32_t)((uint32_t)q[u].w >> 30);
           const double r2d = ex * ex + ey * ey + ez * ez;
-          if (k0 + u * TPP < n && r2d < s_rc2[ab]) {
+          // slots past the row hold the particle itself (r^2 = 0): one
+          // non-short-circuit condition, so the species word is read with
+          // the rest of the record
+          const PairRec& pr = s_pr[ab];
+          if ((r2d > 0.0) & (r2d < pr.rc2)) {
             const float r2 = (float)r2d;
             const float ddx = (float)ex, ddy = (float)ey, ddz = (float)ez;
             const float rinv = __builtin_amdgcn_rsqf(r2);
             const float r2inv = rinv * rinv;
-            const float sr2 = P.sig2[ab] * r2inv;
+            const float sr2 = pr.sig2 * r2inv;
             const float sr6 = sr2 * sr2 * sr2;
             const float sr12 = sr6 * sr6;
-            const float fr = (P.f12[ab] * sr12 + P.f6[ab] * sr6) * r2inv + P.fs[ab] * rinv;
+            const float fr = (pr.f12 * sr12 + pr.f6 * sr6) * r2inv + pr.fs * rinv;
             fx += fr * ddx;
             fy += fr * ddy;
             fz += fr * ddz;
             if constexpr (EN) {
-              pe_i += P.c12[ab] * sr12 + P.c6[ab] * sr6 - P.vc[ab] -
-                      (r2 * rinv - P.rc[ab]) * P.fs[ab];
+              pe_i += pr.c12 * sr12 + pr.c6 * sr6 - pr.vc - (r2 * rinv - pr.rc) * pr.fs;
               w_i += fr * r2;
             }
           }
@@ -295,7 +324,7 @@ __global__ __launch_bounds__(kTile) void k_force(
           }
           const int32_t ab = ti * 4 + (int32_t)q[u].w;
           const double r2 = dx * dx + dy * dy + dz * dz;
-          if (k0 + u * TPP < n && r2 < P.rc2[ab]) {
+          if ((r2 > 0.0) & (r2 < P.rc2[ab])) {  // slots past the row: self, r^2 = 0
             const double rinv = rsqrt_nr(r2);
             const double r2inv = rinv * rinv;
             const double sr2 = P.sig2[ab] * r2inv;
