@@ -86,6 +86,43 @@ def test_cells_lists_forces_fp64(torch_cuda, n, seed, kw):
     assert ob["n_rebuild"] == 1
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dense_cells_groups_and_passes(torch_cuda, precision):
+    """One cutoff of 3.0 for every pair in a 2,048-particle box: 3 cells per
+    side of ~4.0, ~76 particles per cell, so the list build takes each cell's
+    home particles in three groups, and the 27-cell neighbourhood is the
+    whole box (2,048 candidates: three passes of chunks, the later ones
+    starting at each home's running count).  Lists bit-exact (canonical),
+    forces within the bar, before and after steps."""
+    from paper_1105_5613_amd import System, make_params
+    say(f"case dense cells precision={precision}")
+    eps, sig, rc, mass = initconf.mixture_tables(global_rc=3.0)
+    s = initconf.fcc_system(2048, seed=31, temperature=1.5)
+    sysm = System(make_params(eps, sig, rc, mass, skin=SKIN, dt=0.005, precision=precision),
+                  [2048], [s["L"]])
+    sysm.set_state(s["x"], s["v"], s["type"])
+    po = oracle.make_params(eps, sig, rc, mass, skin=SKIN)
+    for k in range(2):
+        if k:
+            sysm.step(12)
+        x = sysm.get_state()[0].cpu().numpy()
+        sysm.build_cells()
+        assert sysm.replica_info(0)["nc"] == 3
+        xw, _, cell, cs, order, nc = oracle.build_cells(po, x, s["L"])
+        assert int(np.max(np.diff(cs))) > 64, "no cell holds three groups"
+        count, ids = oracle.build_nlist(po, xw, s["type"], s["L"], cell, cs, order, nc)
+        gcount, gids = sysm.get_neighbors(0, cap=ids.shape[1])
+        assert np.array_equal(gcount, count)
+        assert np.array_equal(canonical(gcount, gids), canonical(count, ids))
+        sysm.forces()
+        F = sysm.get_forces().cpu().numpy()
+        Fo, _, _ = oracle.forces_list(po, xw, s["type"], s["L"], count, ids)
+        e = floored_err(F, Fo)
+        say(f"  after {12 * k} steps: max per cell {int(np.max(np.diff(cs)))}, force error {e:.3e}")
+        assert e <= (1e-12 if precision == 0 else 1e-5)
+    sysm.close()
+
+
 def boundary_state(seed):
     """4,000-particle FCC state whose lattice planes coincide with the cell
     faces (cell side = 2 lattice constants): every coordinate within 0.05 of a
