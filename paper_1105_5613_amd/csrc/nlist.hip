@@ -139,17 +139,42 @@ static_assert(kCwGroup == 32, "the write phase gives each home two lanes of the 
 static_assert(kCwHomes == 3 || kCwHomes == 4,
               "the home loop leaves at most one block of 2 and one of 1");
 
-// lo[l] = low word of m, hi[l] = high word, for the wave-uniform lane l: two
-// v_writelane with the lane in M0 (the clang in use has no builtin for it,
-// and a lane select in another scalar register would break the one-scalar
-// operand limit).  Lanes other than l keep their values.  m is usually the
-// scalar result of the vector compare just before; the compiler inserts no
-// wait states inside inline asm, so the block starts with the longest one a
-// lane operation needs after a vector write of a scalar register it reads.
-__device__ inline void write_lanes(uint32_t& lo, uint32_t& hi, uint64_t m, int32_t l) {
-  asm volatile("s_nop 4\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
-               : "+v"(lo), "+v"(hi)
-               : "s"((uint32_t)m), "s"((uint32_t)(m >> 32)), "{m0}"(l));
+// lo[l + u] = low word of m[u], hi[l + u] = high word, for the wave-uniform
+// lane l and u < U: v_writelane with the lane in M0 (the clang in use has no
+// builtin for it, and a lane select in another scalar register would break
+// the one-scalar-operand limit), M0 stepped between the pairs.  Lanes not
+// written keep their values.  The m[u] are usually the scalar results of the
+// vector compares just before; the compiler inserts no wait states inside
+// inline asm, so the block starts with the longest one a lane operation needs
+// after a vector write of a scalar register it reads (one wait for all U).
+template <int U>
+__device__ inline void write_lanes(uint32_t& lo, uint32_t& hi, const uint64_t (&m)[U], int32_t l) {
+#define MDK_WL(a, b) "v_writelane_b32 %0, %" #a ", m0\n\tv_writelane_b32 %1, %" #b ", m0"
+#define MDK_S(u) "s"((uint32_t)m[u]), "s"((uint32_t)(m[u] >> 32))
+  if constexpr (U == 1) {
+    asm volatile("s_nop 4\n\t" MDK_WL(3, 4) : "+v"(lo), "+v"(hi), "+{m0}"(l) : MDK_S(0));
+  } else if constexpr (U == 2) {
+    asm volatile("s_nop 4\n\t" MDK_WL(3, 4) "\n\ts_add_u32 m0, m0, 1\n\t" MDK_WL(5, 6)
+                 : "+v"(lo), "+v"(hi), "+{m0}"(l)
+                 : MDK_S(0), MDK_S(1)
+                 : "scc");
+  } else if constexpr (U == 3) {
+    asm volatile("s_nop 4\n\t" MDK_WL(3, 4) "\n\ts_add_u32 m0, m0, 1\n\t" MDK_WL(5, 6)
+                 "\n\ts_add_u32 m0, m0, 1\n\t" MDK_WL(7, 8)
+                 : "+v"(lo), "+v"(hi), "+{m0}"(l)
+                 : MDK_S(0), MDK_S(1), MDK_S(2)
+                 : "scc");
+  } else {
+    static_assert(U == 4, "blocks of 1 to 4 homes");
+    asm volatile("s_nop 4\n\t" MDK_WL(3, 4) "\n\ts_add_u32 m0, m0, 1\n\t" MDK_WL(5, 6)
+                 "\n\ts_add_u32 m0, m0, 1\n\t" MDK_WL(7, 8) "\n\ts_add_u32 m0, m0, 1\n\t"
+                 MDK_WL(9, 10)
+                 : "+v"(lo), "+v"(hi), "+{m0}"(l)
+                 : MDK_S(0), MDK_S(1), MDK_S(2), MDK_S(3)
+                 : "scc");
+  }
+#undef MDK_S
+#undef MDK_WL
 }
 
 // LDS written by some lanes of the wave and read by others: order the
@@ -350,11 +375,13 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
             ra[u] = (ax * ax + ay * ay) + az * az;
             tha[u] = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
           }
+          uint64_t m[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const bool hit = SELF ? ((k != i0 + u) & (ra[u] < tha[u])) : ra[u] < tha[u];
-            write_lanes(mlo, mhi, __builtin_amdgcn_ballot_w64(hit), h + u);
+            m[u] = __builtin_amdgcn_ballot_w64(hit);
           }
+          write_lanes<U>(mlo, mhi, m, h);
           h += U;
         };
         auto homes = [&](auto self_tag) {
