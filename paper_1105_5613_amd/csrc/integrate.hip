@@ -106,10 +106,28 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
                                                         double* __restrict__ lam,
                                                         int32_t* __restrict__ rebuild,
                                                         md_obs* __restrict__ obs, DevState* st) {
-  __shared__ double red[5][kRedThreads];
+  __shared__ double red[5][kRedThreads / 64];
   if (halted(st)) return;  // the step was not taken (kHalt)
   const int32_t r = blockIdx.x;
   const RepDesc R = reps[r];
+  // thread 0's per-replica inputs, fetched before the sums so that their
+  // latency overlaps them (only this block reads or writes index r)
+  md_obs o;
+  int64_t kc = 0;
+  int32_t rb = 0;
+  double tt0 = 0.0, tt1 = 0.0, pend = 0.0;
+  if (threadIdx.x == 0) {
+    o = obs[r];
+    if (step) {
+      kc = kcall[r];
+      rb = rebuild[r];
+      if (ta.thermo) {
+        tt0 = ta.T0[r];
+        tt1 = ta.T1[r];
+      }
+      if (drift.src) pend = drift.pend[r];
+    }
+  }
   double s[3] = {0.0, 0.0, 0.0}, c[3] = {0.0, 0.0, 0.0};
   double m = 0.0;   // largest squared displacement of this step's drift
   double mn = 0.0;  // ... of the next step's drift (fused force launch)
@@ -132,32 +150,42 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
       for (int32_t b = R.tile0 + threadIdx.x; b < R.tile1; b += kRedThreads)
         m = fmax(m, dmax[b]);
   }
-  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k] + c[k];
-  red[3][threadIdx.x] = m;
-  red[4][threadIdx.x] = mn;
-  __syncthreads();
-  for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
-    if (threadIdx.x < h) {
-      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
-      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + h]);
-      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + h]);
-    }
-    __syncthreads();
+  // each wave's totals by a butterfly over its lanes, then the wave totals
+  // in wave order by thread 0: a fixed order, one barrier
+  double v[5] = {s[0] + c[0], s[1] + c[1], s[2] + c[2], m, mn};
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], d, 64);
+    v[3] = fmax(v[3], __shfl_xor(v[3], d, 64));
+    v[4] = fmax(v[4], __shfl_xor(v[4], d, 64));
   }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  const double pe = red[0][0], w = red[1][0];
-  double ke = red[2][0];
-  md_obs o = obs[r];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) v[k] = red[k][0];
+  for (int q = 1; q < kRedThreads / 64; ++q) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += red[k][q];
+    v[3] = fmax(v[3], red[3][q]);
+    v[4] = fmax(v[4], red[4][q]);
+  }
+  const double pe = v[0], w = v[1];
+  double ke = v[2];
   if (energy) {
     o.pe = pe;
     o.virial = w;
   }
   o.T_target = 0.0;
-  if (step) o.max_disp = sqrt(drift.src ? drift.pend[r] : red[3][0]);
+  if (step) o.max_disp = sqrt(drift.src ? pend : v[3]);
   if (step) {
-    const int64_t k = ++kcall[r];
+    const int64_t k = kc + 1;
+    kcall[r] = k;
     if (ta.thermo) {
-      const double t0 = ta.T0[r], t1 = ta.T1[r];
+      const double t0 = tt0, t1 = tt1;
       double tt = t0;
       if (ta.ramp > 0) {
         double f = (double)k / (double)ta.ramp;
@@ -171,10 +199,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
       o.T_target = tt;
     }
     o.step += 1;
-    if (rebuild[r]) o.n_rebuild += 1;
+    if (rb) o.n_rebuild += 1;
     if (drift.next) {
       // the next step's positions are drifted already: its rebuild decision
-      const double mx = red[4][0];
+      const double mx = v[4];
       const int32_t nb = mx > R.half_skin2 ? 1 : 0;
       drift.pend[r] = mx;
       rebuild[r] = nb;
@@ -192,7 +220,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RepDesc* __restric
   }
   obs[r] = o;
   if (step && ta.log_every > 0) {
-    const int64_t k = kcall[r];
+    const int64_t k = kc + 1;
     if (k % ta.log_every == 0) {
       const int64_t idx = k / ta.log_every - 1;
       if (idx >= 0 && idx < ta.nlog) ta.log[idx * gridDim.x + r] = o;
