@@ -437,27 +437,36 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
           (uint32_t)hl +
           (((gbase & (kSlice - 1)) + hl) >= kSlice ? (uint32_t)(cap - 1) * (uint32_t)kSlice : 0u);
       const uint32_t loff = hslot + (uint32_t)(cnt_h + rbeg) * (uint32_t)kSlice;
-      // the word after the current one, read ahead: a lane whose word is used
-      // up (some lane nearly every iteration) takes it without waiting
-      uint32_t nxt = (nseg > 0 && wi + 1 < nwords) ? hits[(wi + 1) * kCwGroup + hl] : 0u;
-      for (int32_t t = 0; t < half; ++t) {
-        if (t < nseg) {
-          // the next set bit; t < nseg leaves one in words wi.. (the bound
-          // on wi only keeps every read inside the pass's words)
-          if (cur == 0u && wi + 1 < nwords) {
-            ++wi;
-            cur = nxt;
-            nxt = wi + 1 < nwords ? hits[(wi + 1) * kCwGroup + hl] : 0u;
-            while (cur == 0u && wi + 1 < nwords) {  // an empty word: rare
-              ++wi;
-              cur = nxt;
-              nxt = wi + 1 < nwords ? hits[(wi + 1) * kCwGroup + hl] : 0u;
-            }
+      // lane: rows [0, nseg) of its segment.  An iteration stores the next
+      // row; when the lane's word is used up it first takes the word read
+      // ahead, and the word after that is read with no select on its value,
+      // so that read stays in flight beside the entry read instead of being
+      // waited for (the index clamps only keep reads inside the pass's
+      // words; t < nseg leaves a set bit in words wi..).  A lane that meets
+      // an empty word (rare) spends an iteration on it and stores its later
+      // rows one iteration late; every lane is done within half + nwords
+      // iterations (at most half rows, at most one word change per word).
+      uint32_t nxt = hits[(wi + 1 < nwords ? wi + 1 : wi) * kCwGroup + hl];
+      int32_t r = 0;
+      const int32_t tmax = half + nwords;
+      for (int32_t t = 0; t < tmax; ++t) {
+        if (!__builtin_amdgcn_ballot_w64(r < nseg)) break;
+        if (r < nseg) {
+          if (cur == 0u) {
+            wi = wi + 1 < nwords ? wi + 1 : wi;
+            // the copy as an instruction of its own, kept above the read:
+            // the new word then lands in nxt's own register and nothing
+            // waits for it here
+            asm volatile("v_mov_b32 %0, %1" : "=v"(cur) : "v"(nxt));
+            __builtin_amdgcn_sched_barrier(0);
+            nxt = hits[(wi + 1 < nwords ? wi + 1 : wi) * kCwGroup + hl];
           }
-          const uint32_t b = (uint32_t)__builtin_ctz(cur | 0x80000000u);
-          cur &= cur - 1u;
-          E* const rowt = grow + (size_t)t * kSlice;  // wave-uniform
-          rowt[loff] = (E)ent[wi * 32 + (int32_t)b];
+          if (cur != 0u) {
+            const uint32_t b = (uint32_t)__builtin_ctz(cur);
+            cur &= cur - 1u;
+            grow[loff + (uint32_t)r * (uint32_t)kSlice] = (E)ent[wi * 32 + (int32_t)b];
+            ++r;
+          }
         }
       }
       cntv += passv;
