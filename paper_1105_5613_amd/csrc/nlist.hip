@@ -228,7 +228,9 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
   __shared__ int32_t s_l0[kCwWaves][27];     // TILE: first LDS slot of piece p in the tile layout
   __shared__ int32_t s_rowsz[kCwWaves][9];   // TILE: slots of tile row q
   __shared__ uint32_t s_ent[kCwWaves][kCwChunks * 64];              // entry of each candidate
-  __shared__ uint32_t s_hits[kCwWaves][2 * kCwChunks * kCwGroup];   // [word][home] hit bits
+  // [word][home] hit bits, and one word more that the write phase's read-ahead
+  // may touch past the last word of a full pass (its value is never used)
+  __shared__ uint32_t s_hits[kCwWaves][(2 * kCwChunks + 1) * kCwGroup];
   if (!st->any_rebuild) return;  // whole block: one flag load when nothing rebuilds
   if (threadIdx.x < 16) s_thr[threadIdx.x] = tab->thr[threadIdx.x];
   __syncthreads();
@@ -441,12 +443,15 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
       // row; when the lane's word is used up it first takes the word read
       // ahead, and the word after that is read with no select on its value,
       // so that read stays in flight beside the entry read instead of being
-      // waited for (the index clamps only keep reads inside the pass's
-      // words; t < nseg leaves a set bit in words wi..).  A lane that meets
-      // an empty word (rare) spends an iteration on it and stores its later
+      // waited for (t < nseg leaves a set bit in words wi.., so a refill
+      // never passes the last word; the clamp on wi and the spare word only
+      // keep every access inside the wave's arrays).  A lane that meets an
+      // empty word (rare) spends an iteration on it and stores its later
       // rows one iteration late; every lane is done within half + nwords
       // iterations (at most half rows, at most one word change per word).
-      uint32_t nxt = hits[(wi + 1 < nwords ? wi + 1 : wi) * kCwGroup + hl];
+      uint32_t nxt = hits[(wi + 1) * kCwGroup + hl];
+      const uint32_t* ew = ent + wi * 32;  // entries of the current word
+      E* rowp = grow + loff;               // the lane's next row slot
       int32_t r = 0;
       const int32_t tmax = half + nwords;
       for (int32_t t = 0; t < tmax; ++t) {
@@ -454,17 +459,19 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
         if (r < nseg) {
           if (cur == 0u) {
             wi = wi + 1 < nwords ? wi + 1 : wi;
+            ew = ent + wi * 32;
             // the copy as an instruction of its own, kept above the read:
             // the new word then lands in nxt's own register and nothing
             // waits for it here
             asm volatile("v_mov_b32 %0, %1" : "=v"(cur) : "v"(nxt));
             __builtin_amdgcn_sched_barrier(0);
-            nxt = hits[(wi + 1 < nwords ? wi + 1 : wi) * kCwGroup + hl];
+            nxt = hits[(wi + 1) * kCwGroup + hl];
           }
           if (cur != 0u) {
             const uint32_t b = (uint32_t)__builtin_ctz(cur);
             cur &= cur - 1u;
-            grow[loff + (uint32_t)r * (uint32_t)kSlice] = (E)ent[wi * 32 + (int32_t)b];
+            *rowp = (E)ew[b];
+            rowp += kSlice;
             ++r;
           }
         }
