@@ -230,9 +230,13 @@ int mdref_build_nlist(const mdref_params* p, int64_t n, double L, int32_t nc,
             for (int32_t k = cell_start[cn]; k < cell_start[cn + 1]; ++k) {
               int32_t j = order[k];
               if (j == i) continue;
-              double ex = (x[3 * (int64_t)j + 0] + shx) - xi[0];
-              double ey = (x[3 * (int64_t)j + 1] + shy) - xi[1];
-              double ez = (x[3 * (int64_t)j + 2] + shz) - xi[2];
+              /* the difference first, then the box shift: exchanging i and
+               * j (and s for -s) negates every step exactly, so the test
+               * is symmetric and the list pairs are those of the third-law
+               * halving (section "Grid-search method") */
+              double ex = (x[3 * (int64_t)j + 0] - xi[0]) + shx;
+              double ey = (x[3 * (int64_t)j + 1] - xi[1]) + shy;
+              double ez = (x[3 * (int64_t)j + 2] - xi[2]) + shz;
               double r2 = (ex * ex + ey * ey) + ez * ez;
               if (r2 < thr[AB(ti, type[j])]) {
                 if (cnt < cap) ids[i * (int64_t)cap + cnt] = j;

@@ -75,8 +75,10 @@ int mdref_build_cells(int64_t n, double L, int32_t nc, double inv_cell,
                       int32_t* cell_start, int32_t* order);
 
 /* Full neighbour list over the 27-cell stencil: j in list(i) iff
- * r^2 < (rc_ab + skin)^2.  Rows ids [n][cap] in traversal order, count [n]
- * is the true count.  Returns 1 if any count exceeded cap. */
+ * r^2 < (rc_ab + skin)^2, with d = (x_j - x_i) + s L for the stencil image s
+ * of j and r^2 = (dx dx + dy dy) + dz dz (symmetric in i and j, bit for
+ * bit).  Rows ids [n][cap] in traversal order, count [n] is the true count.
+ * Returns 1 if any count exceeded cap. */
 int mdref_build_nlist(const mdref_params* p, int64_t n, double L, int32_t nc,
                       const double* x, const int32_t* type,
                       const int32_t* cell, const int32_t* cell_start,

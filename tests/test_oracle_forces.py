@@ -230,6 +230,46 @@ def test_cells_and_lists_vs_definition(oracle_lib, n, seed, shift):
     assert wc.sum() == pytest.approx(wb, rel=1e-12)
 
 
+def test_list_symmetric_at_the_threshold_across_a_face(oracle_lib):
+    """Two particles on opposite faces of the box, with the cut-off placed
+    strictly between the two values that a shift-first displacement
+    ((x_j + s L) - x_i) takes in the two directions.  The list must still be
+    symmetric, as the third-law halving of the pair count presumes (section
+    "Grid-search method"), and agree with d = (x_j - x_i) + s L, whose
+    exchange negates every rounding step exactly."""
+    o = oracle_lib
+    L = 29.3
+    rng = np.random.default_rng(7)
+    for _ in range(200000):
+        a, b = rng.uniform(0.2, 1.1, size=2)
+        xa, xb = L - a, b
+        if not (xa < L):
+            continue
+        fwd = ((xb + L) - xa) ** 2   # home xa, partner xb seen at xb + L
+        bwd = ((xa - L) - xb) ** 2   # home xb, partner xa seen at xa - L
+        lo, hi = min(fwd, bwd), max(fwd, bwd)
+        # a cut-off rc with lo < rc * rc < hi (skin 0: the threshold is rc^2)
+        rc = math.sqrt(0.5 * (lo + hi))
+        for _ in range(8):
+            if rc * rc <= lo:
+                rc = np.nextafter(rc, np.inf)
+            elif rc * rc >= hi:
+                rc = np.nextafter(rc, 0.0)
+        if lo < rc * rc < hi:
+            break
+    else:
+        pytest.fail("no pair with a threshold between the two shift-first values")
+    p = o.make_params([[1.0]], [[0.3]], [[rc]], [1.0], skin=0.0)
+    x = np.array([[xa, 5.0, 5.0], [xb, 5.0, 5.0]])
+    t = np.zeros(2, np.int32)
+    xw, img, cell, cs, order, nc = o.build_cells(p, x, L)
+    assert nc >= 3 and np.array_equal(xw, x)
+    count, ids = o.build_nlist(p, xw, t, L, cell, cs, order, nc)
+    want = ((xb - xa) + L) ** 2 < rc * rc
+    assert ((xa - xb) - L) ** 2 == ((xb - xa) + L) ** 2
+    assert count.tolist() == [int(want), int(want)]
+
+
 def test_small_box_single_cell(oracle_lib):
     """L < 3 (rc + skin): one cell, the list falls back to the minimum image."""
     o = oracle_lib
