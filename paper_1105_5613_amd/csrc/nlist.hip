@@ -5,7 +5,8 @@
 // search fills a full (both directions) neighbour list with a skin, so the
 // force kernel can reuse it for several steps.  The inclusion test must give
 // exactly the same set as a plain FP64 evaluation of
-//     d = (x_j + s L) - x_i,  r^2 = (dx dx + dy dy) + dz dz  <  (rc_ab + skin)^2
+//     d = (x_j - x_i) + s L,  r^2 = (dx dx + dy dy) + dz dz  <  (rc_ab + skin)^2
+// (exchanging i and j negates every step exactly: the test is symmetric)
 // so this file is compiled without FMA contraction (also forced below).
 //
 // List entry: sorted index j (26 bits) | a 6-bit code, two bits per axis in
@@ -336,12 +337,16 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
         const int32_t k = valid ? s_k0[w][p] + (v - s_pre[w][p]) : h0;
         const uint32_t code = (uint32_t)s_code[w][p];
         const double4 q = pos_tmp[k];
-        // the periodic shift of the piece: x_j + s L; lanes past the last
-        // candidate sit far away, so their test fails without a mask
+        // the periodic shift of the piece, added after the difference:
+        // d = (x_j - x_i) + s L (exactly antisymmetric under exchange); a
+        // chunk with no shifted candidate skips the adds (x + 0 = x up to
+        // the sign of a zero, which r^2 does not see).  Lanes past the last
+        // candidate sit far away, so their test fails without a mask.
         const double sx = (double)(((int32_t)(code << 4)) >> 30) * R.L;
         const double sy = (double)(((int32_t)(code << 2)) >> 30) * R.L;
         const double sz = (double)(((int32_t)code) >> 30) * R.L;
-        const double xs = valid ? q.x + sx : kFar, ys = q.y + sy, zs = q.z + sz;
+        const double xq = valid ? q.x : kFar, yq = q.y, zq = q.z;
+        const bool shifted = __builtin_amdgcn_ballot_w64(valid && code != 0u) != 0;
         const int32_t tj = (int32_t)q.w;  // thr[4 ta + tj] is the pair (ta, tj)
         const double t0 = s_thr[tj], t1 = s_thr[4 + tj], t2 = s_thr[8 + tj], t3 = s_thr[12 + tj];
         const double d01 = t1 - t0;
@@ -365,15 +370,21 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
         // U home particles (wave-uniform, scalar loads): the distances
         // first (independent work), then the ballots; blocks of HPI, then
         // one of 2 and one of 1 for the rest, all with the same code
-        auto block = [&](auto self_tag, auto u_tag) {
+        auto block = [&](auto self_tag, auto shift_tag, auto u_tag) {
           constexpr bool SELF = decltype(self_tag)::value;
+          constexpr bool SHIFT = decltype(shift_tag)::value;
           constexpr int U = decltype(u_tag)::value;
           const int32_t i0 = __builtin_amdgcn_readfirstlane(gbase + h);
           double ra[U], tha[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const double4 pa = pos_tmp[i0 + u];
-            const double ax = xs - pa.x, ay = ys - pa.y, az = zs - pa.z;
+            double ax = xq - pa.x, ay = yq - pa.y, az = zq - pa.z;
+            if constexpr (SHIFT) {
+              ax = ax + sx;
+              ay = ay + sy;
+              az = az + sz;
+            }
             ra[u] = (ax * ax + ay * ay) + az * az;
             tha[u] = pick_thr<NT>(pa.w, t0, d01, t1, t2, t3);
           }
@@ -386,15 +397,22 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
           write_lanes<U>(mlo, mhi, m, h);
           h += U;
         };
-        auto homes = [&](auto self_tag) {
-          while (h + HPI <= gn) block(self_tag, std::integral_constant<int, HPI>{});
-          if (h + 2 <= gn) block(self_tag, std::integral_constant<int, 2>{});
-          if (h < gn) block(self_tag, std::integral_constant<int, 1>{});
+        auto homes = [&](auto self_tag, auto shift_tag) {
+          while (h + HPI <= gn) block(self_tag, shift_tag, std::integral_constant<int, HPI>{});
+          if (h + 2 <= gn) block(self_tag, shift_tag, std::integral_constant<int, 2>{});
+          if (h < gn) block(self_tag, shift_tag, std::integral_constant<int, 1>{});
         };
-        if (self_chunk)
-          homes(std::true_type{});
-        else
-          homes(std::false_type{});
+        if (shifted) {
+          if (self_chunk)
+            homes(std::true_type{}, std::true_type{});
+          else
+            homes(std::false_type{}, std::true_type{});
+        } else {
+          if (self_chunk)
+            homes(std::true_type{}, std::false_type{});
+          else
+            homes(std::false_type{}, std::false_type{});
+        }
         if (lane < kCwGroup) {
           hits[(2 * ci) * kCwGroup + lane] = mlo;
           hits[(2 * ci + 1) * kCwGroup + lane] = mhi;
