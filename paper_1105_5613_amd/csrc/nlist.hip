@@ -110,9 +110,11 @@ __global__ __launch_bounds__(kTile) void k_nlist(
 // One wave per home cell (nc >= 3), in two phases per group of at most
 // kCwGroup home particles.
 //
-// Test phase: the candidates of the cell -- the 9 neighbour rows, each one to
-// three contiguous particle ranges with their periodic shift -- are packed 64
-// to a chunk, one candidate per lane, with x_j + s L formed once per chunk.
+// Test phase: the candidates of the cell -- the 27 stencil cells as single
+// contiguous particle ranges (gather path: the home cell, the 13 forward
+// cells, the 13 backward ones), or the 9 neighbour rows of one to three
+// ranges each (staged path), with their periodic shift -- are packed 64 to a
+// chunk, one candidate per lane.
 // For every home particle (wave-uniform loop, coordinates through scalar
 // loads) each lane tests its candidate.  The ballot of the hits is the whole
 // result: its two 32-bit words go to lane h of two registers (one
@@ -228,6 +230,7 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
   __shared__ int32_t s_code[kCwWaves][27];   // image code of piece p (shift -1/0/1 per axis)
   __shared__ int32_t s_l0[kCwWaves][27];     // TILE: first LDS slot of piece p in the tile layout
   __shared__ int32_t s_rowsz[kCwWaves][9];   // TILE: slots of tile row q
+  __shared__ int32_t s_ecode[kCwWaves][27];  // gather path: entry code of piece p's particles
   __shared__ uint32_t s_ent[kCwWaves][kCwChunks * 64];              // entry of each candidate
   // [word][home] hit bits, and one word more that the write phase's read-ahead
   // may touch past the last word of a full pass (its value is never used)
@@ -251,69 +254,108 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
   uint32_t* const ent = s_ent[w];
   uint32_t* const hits = s_hits[w];
 
-  // pieces: lane q < 9 builds neighbour row q (dz = q/3 - 1, dy = q%3 - 1)
-  if (lane < 9) {
-    int32_t nz, sz, ny, sy;
-    stencil_axis(qz, lane / 3 - 1, nc, nz, sz);
-    stencil_axis(qy, lane % 3 - 1, nc, ny, sy);
-    const int32_t rowbase = R.coff + (nz * nc + ny) * nc;
-    const int p = 3 * lane;
-    // left wrap, main, right wrap; empty pieces have zero length
-    s_k0[w][p] = cell_start[rowbase + nc - 1];
-    s_code[w][p] = (int32_t)image_code(-1, sy, sz);
-    const int32_t nl = qx - 1 < 0 ? cell_start[rowbase + nc] - cell_start[rowbase + nc - 1] : 0;
-    const int32_t lo = qx - 1 < 0 ? 0 : qx - 1, hi = qx + 1 >= nc ? nc - 1 : qx + 1;
-    s_k0[w][p + 1] = cell_start[rowbase + lo];
-    s_code[w][p + 1] = (int32_t)image_code(0, sy, sz);
-    const int32_t nm = cell_start[rowbase + hi + 1] - cell_start[rowbase + lo];
-    s_k0[w][p + 2] = cell_start[rowbase];
-    s_code[w][p + 2] = (int32_t)image_code(1, sy, sz);
-    const int32_t nr = qx + 1 >= nc ? cell_start[rowbase + 1] - cell_start[rowbase] : 0;
-    s_pre[w][p] = nl;  // lengths for now
-    s_pre[w][p + 1] = nm;
-    s_pre[w][p + 2] = nr;
-    if constexpr (TILE) {
-      // the tile's row q: left piece (logical cell a-1 < 0), main cells, right
-      // piece (logical cell a+nx >= nc); offsets of this cell's pieces in it
-      const RowTile T = rtiles[cell_tile[c]];
-      const int32_t tlo = T.a - 1, thi = T.a + T.nx;
-      const int32_t mlo = tlo < 0 ? 0 : tlo, mhi = thi >= nc ? nc - 1 : thi;
-      const int32_t lsz = tlo < 0 ? cell_start[rowbase + nc] - cell_start[rowbase + nc - 1] : 0;
-      const int32_t msz = cell_start[rowbase + mhi + 1] - cell_start[rowbase + mlo];
-      const int32_t rsz = thi >= nc ? cell_start[rowbase + 1] - cell_start[rowbase] : 0;
-      s_rowsz[w][lane] = lsz + msz + rsz;
-      s_l0[w][p] = 0;
-      s_l0[w][p + 1] = lsz + (cell_start[rowbase + lo] - cell_start[rowbase + mlo]);
-      s_l0[w][p + 2] = lsz + msz;
+  int32_t own_slot = 13;  // piece holding the home cell's particles
+  if constexpr (!TILE) {
+    // gather path: the 27 cells as single-cell pieces, the home cell first,
+    // then the offsets after (0,0,0) in (dz, dy, dx) order, then those
+    // before it from the nearest back; lane q < 27 builds offset q.  The row
+    // order this gives (own cell, forward half, backward half) makes the
+    // force kernel's gathers of a wave's particles hit the same cells at
+    // the same entry index more often than the (dz, dy, dx) order.
+    if (lane < 27) {
+      const int32_t ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
+      int32_t nx, sx, ny, sy, nz, sz;
+      stencil_axis(qx, ox, nc, nx, sx);
+      stencil_axis(qy, oy, nc, ny, sy);
+      stencil_axis(qz, oz, nc, nz, sz);
+      const int32_t cn = R.coff + (nz * nc + ny) * nc + nx;
+      const int32_t slot = lane == 13 ? 0 : (lane > 13 ? lane - 13 : 26 - lane);
+      s_k0[w][slot] = cell_start[cn];
+      s_pre[w][slot] = cell_start[cn + 1] - cell_start[cn];  // lengths for now
+      const uint32_t code = image_code(sx, sy, sz);
+      s_code[w][slot] = (int32_t)code;
+      // mixed lists: d = c_i - c_j - s nc = -o
+      s_ecode[w][slot] = (int32_t)(dcode ? image_code(-ox, -oy, -oz) : code);
     }
-  }
-  __builtin_amdgcn_wave_barrier();
-  if (lane == 0) {
-    int32_t acc = 0;
-    for (int p = 0; p < 27; ++p) {
-      const int32_t len = s_pre[w][p];
-      s_pre[w][p] = acc;
-      acc += len;
-    }
-    s_pre[w][27] = acc;
-    if constexpr (TILE) {
-      int32_t ro = 0;
-      for (int q = 0; q < 9; ++q) {
-        for (int u = 0; u < 3; ++u) s_l0[w][3 * q + u] += ro;
-        ro += s_rowsz[w][q];
+    own_slot = 0;
+    wave_lds_sync();
+    if (lane == 0) {
+      int32_t acc = 0;
+      for (int p = 0; p < 27; ++p) {
+        const int32_t len = s_pre[w][p];
+        s_pre[w][p] = acc;
+        acc += len;
       }
-      if (ro > kMaxStaged) atomicOr(&st->err, kErrSlots);
+      s_pre[w][27] = acc;
     }
+    wave_lds_sync();
+  } else {
+    // staged path: pieces by neighbour rows; lane q < 9 builds neighbour row q
+    // (dz = q/3 - 1, dy = q%3 - 1)
+    if (lane < 9) {
+      int32_t nz, sz, ny, sy;
+      stencil_axis(qz, lane / 3 - 1, nc, nz, sz);
+      stencil_axis(qy, lane % 3 - 1, nc, ny, sy);
+      const int32_t rowbase = R.coff + (nz * nc + ny) * nc;
+      const int p = 3 * lane;
+      // left wrap, main, right wrap; empty pieces have zero length
+      s_k0[w][p] = cell_start[rowbase + nc - 1];
+      s_code[w][p] = (int32_t)image_code(-1, sy, sz);
+      const int32_t nl = qx - 1 < 0 ? cell_start[rowbase + nc] - cell_start[rowbase + nc - 1] : 0;
+      const int32_t lo = qx - 1 < 0 ? 0 : qx - 1, hi = qx + 1 >= nc ? nc - 1 : qx + 1;
+      s_k0[w][p + 1] = cell_start[rowbase + lo];
+      s_code[w][p + 1] = (int32_t)image_code(0, sy, sz);
+      const int32_t nm = cell_start[rowbase + hi + 1] - cell_start[rowbase + lo];
+      s_k0[w][p + 2] = cell_start[rowbase];
+      s_code[w][p + 2] = (int32_t)image_code(1, sy, sz);
+      const int32_t nr = qx + 1 >= nc ? cell_start[rowbase + 1] - cell_start[rowbase] : 0;
+      s_pre[w][p] = nl;  // lengths for now
+      s_pre[w][p + 1] = nm;
+      s_pre[w][p + 2] = nr;
+      if constexpr (TILE) {
+        // the tile's row q: left piece (logical cell a-1 < 0), main cells, right
+        // piece (logical cell a+nx >= nc); offsets of this cell's pieces in it
+        const RowTile T = rtiles[cell_tile[c]];
+        const int32_t tlo = T.a - 1, thi = T.a + T.nx;
+        const int32_t mlo = tlo < 0 ? 0 : tlo, mhi = thi >= nc ? nc - 1 : thi;
+        const int32_t lsz = tlo < 0 ? cell_start[rowbase + nc] - cell_start[rowbase + nc - 1] : 0;
+        const int32_t msz = cell_start[rowbase + mhi + 1] - cell_start[rowbase + mlo];
+        const int32_t rsz = thi >= nc ? cell_start[rowbase + 1] - cell_start[rowbase] : 0;
+        s_rowsz[w][lane] = lsz + msz + rsz;
+        s_l0[w][p] = 0;
+        s_l0[w][p + 1] = lsz + (cell_start[rowbase + lo] - cell_start[rowbase + mlo]);
+        s_l0[w][p + 2] = lsz + msz;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      int32_t acc = 0;
+      for (int p = 0; p < 27; ++p) {
+        const int32_t len = s_pre[w][p];
+        s_pre[w][p] = acc;
+        acc += len;
+      }
+      s_pre[w][27] = acc;
+      if constexpr (TILE) {
+        int32_t ro = 0;
+        for (int q = 0; q < 9; ++q) {
+          for (int u = 0; u < 3; ++u) s_l0[w][3 * q + u] += ro;
+          ro += s_rowsz[w][q];
+        }
+        if (ro > kMaxStaged) atomicOr(&st->err, kErrSlots);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
-  __builtin_amdgcn_wave_barrier();
   const int32_t ncand = s_pre[w][27];
 
   // groups of at most kCwGroup home particles, of equal size
   const int32_t ngrp = (nh + kCwGroup - 1) / kCwGroup;
   const int32_t gsz = ngrp ? (nh + ngrp - 1) / ngrp : 1;
-  // first packed candidate of the cell's own particles (the main piece of the
-  // central row, the only candidates that can be a home particle itself)
-  const int32_t sv0 = s_pre[w][13] + (h0 - s_k0[w][13]);
+  // first packed candidate of the cell's own particles (the home cell's
+  // piece, or the main piece of the central row: the only candidates that
+  // can be a home particle itself)
+  const int32_t sv0 = s_pre[w][own_slot] + (h0 - s_k0[w][own_slot]);
   for (int32_t g0 = 0; g0 < nh; g0 += gsz) {
     const int32_t gn = nh - g0 < gsz ? nh - g0 : gsz;
     const int32_t gbase = __builtin_amdgcn_readfirstlane(h0 + g0);  // wave-uniform
@@ -353,14 +395,8 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
         uint32_t entry;
         if constexpr (TILE) {
           entry = (uint32_t)((s_l0[w][p] + (v - s_pre[w][p])) & 0x3fff) | ((uint32_t)tj << 14);
-        } else if (dcode) {
-          // d = c_i - c_j - s nc: -dy, -dz of the row; along x from the
-          // partner's build-time cell and the piece's shift
-          const int32_t row = p / 3, kind = p - 3 * row;
-          const int32_t cxj = cell_coord(q.x, R.inv_cell, nc);
-          entry = (uint32_t)k | image_code(qx - cxj - (kind - 1) * nc, 1 - row % 3, 1 - row / 3);
         } else {
-          entry = (uint32_t)k | code;
+          entry = (uint32_t)k | (uint32_t)s_ecode[w][p];
         }
         ent[ci * 64 + lane] = entry;
         // chunks that miss the group's own particles skip the self test
