@@ -111,8 +111,8 @@ __global__ __launch_bounds__(kTile) void k_nlist(
 // kCwGroup home particles.
 //
 // Test phase: the candidates of the cell -- the 27 stencil cells as single
-// contiguous particle ranges (gather path: the home cell, the 13 forward
-// cells, the 13 backward ones), or the 9 neighbour rows of one to three
+// contiguous particle ranges (gather path: the home cell, then pairs of
+// mirror cells o, -o), or the 9 neighbour rows of one to three
 // ranges each (staged path), with their periodic shift -- are packed 64 to a
 // chunk, one candidate per lane.
 // For every home particle (wave-uniform loop, coordinates through scalar
@@ -257,11 +257,12 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
   int32_t own_slot = 13;  // piece holding the home cell's particles
   if constexpr (!TILE) {
     // gather path: the 27 cells as single-cell pieces, the home cell first,
-    // then the offsets after (0,0,0) in (dz, dy, dx) order, then those
-    // before it from the nearest back; lane q < 27 builds offset q.  The row
-    // order this gives (own cell, forward half, backward half) makes the
-    // force kernel's gathers of a wave's particles hit the same cells at
-    // the same entry index more often than the (dz, dy, dx) order.
+    // then each forward offset o (in (dz, dy, dx) order) followed by its
+    // mirror -o; lane q < 27 builds offset q.  A particle's place in its
+    // cell moves hits between o and -o but hardly changes their sum, so
+    // after every pair the particles of a wave have used about the same
+    // number of entries, and the force kernel's gathers at one entry index
+    // fall in the same cells more often than with rows in (dz, dy, dx) order.
     if (lane < 27) {
       const int32_t ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
       int32_t nx, sx, ny, sy, nz, sz;
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
       stencil_axis(qy, oy, nc, ny, sy);
       stencil_axis(qz, oz, nc, nz, sz);
       const int32_t cn = R.coff + (nz * nc + ny) * nc + nx;
-      const int32_t slot = lane == 13 ? 0 : (lane > 13 ? lane - 13 : 26 - lane);
+      const int32_t slot = lane == 13 ? 0 : (lane > 13 ? 2 * (lane - 13) - 1 : 2 * (13 - lane));
       s_k0[w][slot] = cell_start[cn];
       s_pre[w][slot] = cell_start[cn + 1] - cell_start[cn];  // lengths for now
       const uint32_t code = image_code(sx, sy, sz);
