@@ -20,6 +20,8 @@ Other modes (used to make the committed profiles/ summaries):
   --calibrate-copy          a plain 1 GiB device copy (counter calibration)
   --counters-summary DIRS   turn rocprofv3 --pmc outputs into
                             profiles/force_counters.json
+  --long-drift N            only the energy drift of the 1M FP64 / mixed
+                            forms over an N-step NVE run (one JSON line)
 """
 from __future__ import annotations
 
@@ -36,6 +38,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "particle-steps/sec on 1 MI355X + % HBM roofline; mixed/batched vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 FORCE_SRC = os.path.join(ROOT, "paper_1105_5613_amd", "csrc", "force.hip")
+# the list build fixes the order in which the force kernel gathers, and so
+# its traffic: the counters hold for this pair of sources only
+LIST_SRC = os.path.join(ROOT, "paper_1105_5613_amd", "csrc", "nlist.hip")
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "force_counters.json")
 FP64_OPS_JSON = os.path.join(ROOT, "profiles", "fp64_ops.json")
 FP64_PEAK_TFLOPS = 78.6
@@ -115,13 +120,15 @@ def fp64_flops_per_particle(key: str):
 
 def counters_traffic(key: str):
     """HBM bytes per force launch from the committed rocprofv3 counter runs, or
-    None when the force kernel source changed since the counters were taken."""
+    None when the force kernel or the list build (the gather order) changed
+    since the counters were taken."""
     if not os.path.exists(COUNTERS_JSON):
         return None
     with open(COUNTERS_JSON) as f:
         d = json.load(f)
     ent = d.get("forms", {}).get(key)
-    if not ent or d.get("force_src_sha256") != src_sha():
+    if not ent or d.get("force_src_sha256") != src_sha() or \
+            d.get("list_src_sha256") != src_sha(LIST_SRC):
         return None
     return ent["fetch_kib"] * 1024 * d["copy_factor_fetch"] + \
         ent["write_kib"] * 1024 * d["copy_factor_write"]
@@ -162,9 +169,10 @@ def floored_force_error(F_sel, Fo_sel, frms: float) -> float:
 
 
 def run_drift(precision: int, inputs, path: int = 1, potential: int = 0, global_rc=None,
-              dt: float = 0.005):
-    """D over DRIFT_STEPS NVE steps of a fresh context from the form's initial
-    state (energies every step), so the figure does not depend on --steps."""
+              dt: float = 0.005, steps: int = DRIFT_STEPS):
+    """D over `steps` (default DRIFT_STEPS) NVE steps of a fresh context from
+    the form's initial state (energies every step), so the figure does not
+    depend on --steps."""
     from paper_1105_5613_amd import System, make_params
     import initconf
     eps, sig, rc, mass = initconf.mixture_tables(global_rc=global_rc)
@@ -173,10 +181,10 @@ def run_drift(precision: int, inputs, path: int = 1, potential: int = 0, global_
     n = inputs["n"]
     sysm = System(p, [n], [inputs["L"]])
     sysm.set_state(inputs["x"], inputs["v"], inputs["type"])
-    lg = sysm.step(DRIFT_STEPS, log_every=1)
+    lg = sysm.step(steps, log_every=1)
     sysm.close()
     out = energy_drift(lg["E"][:, 0], n)
-    out["window"] = f"steps {DRIFT_BURN}..{DRIFT_STEPS} of an NVE run from the initial state, " \
+    out["window"] = f"steps {DRIFT_BURN}..{steps} of an NVE run from the initial state, " \
                     f"dt {dt}, E logged every step"
     return out
 
@@ -416,7 +424,7 @@ def counters_summary(args):
     cf, _ = mean_for(args.copy_fetch_dir, "", "FETCH_SIZE", "copy")
     cw, _ = mean_for(args.copy_write_dir, "", "WRITE_SIZE", "copy")
     copy_kib = COPY_BYTES / 1024
-    out = {"force_src_sha256": src_sha(),
+    out = {"force_src_sha256": src_sha(), "list_src_sha256": src_sha(LIST_SRC),
            "copy_bytes": COPY_BYTES, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "copy_factor_fetch": copy_kib / cf, "copy_factor_write": copy_kib / cw,
            "forms": {}, "commands": args.commands}
@@ -454,6 +462,7 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=100,
                     help="steps per captured hipGraph in the batched form (0: direct launches)")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--long-drift", type=int, default=0)
     ap.add_argument("--counters-summary", action="store_true")
     ap.add_argument("--fp64-ops-summary", action="store_true")
     ap.add_argument("--flops-dir")
@@ -486,6 +495,16 @@ def main():
     n = args.n
     log(f"generating inputs n={n}")
     inputs = initconf.fcc_system(n, seed=2, temperature=2.0)
+    if args.long_drift:
+        out = {"particles": n, "steps": args.long_drift, "forms": {}}
+        for f in forms:
+            if f in ("fp64", "mixed"):
+                log(f"drift of form {f} over {args.long_drift} NVE steps")
+                out["forms"][f] = run_drift(1 if f == "mixed" else 0, inputs,
+                                            steps=args.long_drift)
+                log(f"  {f}: D {out['forms'][f]['D']:.3e}")
+        print(json.dumps(out))
+        return
     res = {}
     for f in forms:
         if f not in ("fp64", "mixed"):

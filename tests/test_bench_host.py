@@ -54,16 +54,21 @@ def test_floored_force_error():
 
 
 def test_counter_traffic_needs_the_current_kernel_source(tmp_path, monkeypatch):
-    d = {"force_src_sha256": bench.src_sha(), "copy_factor_fetch": 2.0,
-         "copy_factor_write": 1.0, "forms": {"fp64": {"fetch_kib": 10.0, "write_kib": 3.0}}}
+    # the counters hold for one force kernel and one list build (the order in
+    # which the kernel gathers): a change to either source voids them
+    d = {"force_src_sha256": bench.src_sha(), "list_src_sha256": bench.src_sha(bench.LIST_SRC),
+         "copy_factor_fetch": 2.0, "copy_factor_write": 1.0,
+         "forms": {"fp64": {"fetch_kib": 10.0, "write_kib": 3.0}}}
     p = tmp_path / "c.json"
     p.write_text(json.dumps(d))
     monkeypatch.setattr(bench, "COUNTERS_JSON", str(p))
     assert bench.counters_traffic("fp64") == pytest.approx(10.0 * 1024 * 2.0 + 3.0 * 1024)
     assert bench.counters_traffic("mixed") is None
-    d["force_src_sha256"] = "0" * 64
-    p.write_text(json.dumps(d))
-    assert bench.counters_traffic("fp64") is None
+    for key in ("force_src_sha256", "list_src_sha256"):
+        e = dict(d)
+        e[key] = "0" * 64
+        p.write_text(json.dumps(e))
+        assert bench.counters_traffic("fp64") is None
 
 
 def test_more_than_one_gpu_is_refused():
