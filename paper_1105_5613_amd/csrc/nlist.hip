@@ -313,20 +313,18 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
       s_pre[w][p] = nl;  // lengths for now
       s_pre[w][p + 1] = nm;
       s_pre[w][p + 2] = nr;
-      if constexpr (TILE) {
-        // the tile's row q: left piece (logical cell a-1 < 0), main cells, right
-        // piece (logical cell a+nx >= nc); offsets of this cell's pieces in it
-        const RowTile T = rtiles[cell_tile[c]];
-        const int32_t tlo = T.a - 1, thi = T.a + T.nx;
-        const int32_t mlo = tlo < 0 ? 0 : tlo, mhi = thi >= nc ? nc - 1 : thi;
-        const int32_t lsz = tlo < 0 ? cell_start[rowbase + nc] - cell_start[rowbase + nc - 1] : 0;
-        const int32_t msz = cell_start[rowbase + mhi + 1] - cell_start[rowbase + mlo];
-        const int32_t rsz = thi >= nc ? cell_start[rowbase + 1] - cell_start[rowbase] : 0;
-        s_rowsz[w][lane] = lsz + msz + rsz;
-        s_l0[w][p] = 0;
-        s_l0[w][p + 1] = lsz + (cell_start[rowbase + lo] - cell_start[rowbase + mlo]);
-        s_l0[w][p + 2] = lsz + msz;
-      }
+      // the tile's row q: left piece (logical cell a-1 < 0), main cells, right
+      // piece (logical cell a+nx >= nc); offsets of this cell's pieces in it
+      const RowTile T = rtiles[cell_tile[c]];
+      const int32_t tlo = T.a - 1, thi = T.a + T.nx;
+      const int32_t mlo = tlo < 0 ? 0 : tlo, mhi = thi >= nc ? nc - 1 : thi;
+      const int32_t lsz = tlo < 0 ? cell_start[rowbase + nc] - cell_start[rowbase + nc - 1] : 0;
+      const int32_t msz = cell_start[rowbase + mhi + 1] - cell_start[rowbase + mlo];
+      const int32_t rsz = thi >= nc ? cell_start[rowbase + 1] - cell_start[rowbase] : 0;
+      s_rowsz[w][lane] = lsz + msz + rsz;
+      s_l0[w][p] = 0;
+      s_l0[w][p + 1] = lsz + (cell_start[rowbase + lo] - cell_start[rowbase + mlo]);
+      s_l0[w][p + 2] = lsz + msz;
     }
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
@@ -337,14 +335,12 @@ __global__ __launch_bounds__(64 * kCwWaves) void k_nlist_cells(
         acc += len;
       }
       s_pre[w][27] = acc;
-      if constexpr (TILE) {
-        int32_t ro = 0;
-        for (int q = 0; q < 9; ++q) {
-          for (int u = 0; u < 3; ++u) s_l0[w][3 * q + u] += ro;
-          ro += s_rowsz[w][q];
-        }
-        if (ro > kMaxStaged) atomicOr(&st->err, kErrSlots);
+      int32_t ro = 0;
+      for (int q = 0; q < 9; ++q) {
+        for (int u = 0; u < 3; ++u) s_l0[w][3 * q + u] += ro;
+        ro += s_rowsz[w][q];
       }
+      if (ro > kMaxStaged) atomicOr(&st->err, kErrSlots);
     }
     __builtin_amdgcn_wave_barrier();
   }
