@@ -111,6 +111,12 @@ typedef struct {
                             step; never on the last step of an md_step call, so the state
                             it leaves is complete); 1 = always a separate kick/drift
                             launch */
+  int32_t small_box;     /* 0 = auto: a context of one box of at most 8,192 particles
+                            (and 4,096 cells) rebuilds its cells in one block, and one of
+                            at most 16,384 particles with >= 3 cells per side searches
+                            its list (gather path) with 32 lanes per particle: the same
+                            cells and lists bit for bit, with fewer launches and less
+                            latency at these sizes; 1 = always the general kernels */
 } md_params;
 
 /* Per-replica observables after the last completed step. */

@@ -23,9 +23,9 @@ COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-x", "hip",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Werror", "-Wno-unused-command-line-argument",
           "-I", os.path.join(HERE, "..", "include")]
-PER_FILE = {"nlist.hip": ["-ffp-contract=off"],
+PER_FILE = {"nlist.hip": ["-ffp-contract=off"], "nlist_small.hip": ["-ffp-contract=off"],
             "analysis.hip": ["-ffp-contract=off"]}
-SOURCES = ["cells.hip", "nlist.hip", "force.hip", "force_staged.hip", "force_cells.hip",
+SOURCES = ["cells.hip", "nlist.hip", "nlist_small.hip", "force.hip", "force_staged.hip", "force_cells.hip",
            "integrate.hip", "analysis.hip", "md_api.cpp"]
 
 

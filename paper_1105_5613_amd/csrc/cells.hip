@@ -124,6 +124,36 @@ __device__ inline int32_t cell_coord(double c, double inv_cell, int32_t nc) {
   return q > nc - 1 ? nc - 1 : q;
 }
 
+// Wrap particle i of replica R into the box (image counter and position
+// updated; a coordinate that one wrap does not bring into [0, L) latches
+// kErrStray) and return its cell, numbered from the first cell of all
+// replicas.
+__device__ inline int32_t bin_particle(int32_t i, const RepDesc& R, double4* __restrict__ pos,
+                                       const int32_t* __restrict__ id, int32_t* __restrict__ img,
+                                       DevState* st) {
+  const double4 p0 = pos[i];
+  double4 p = p0;
+  int32_t bad = 0;
+  int32_t dx = wrap1(p.x, R.L, bad);
+  int32_t dy = wrap1(p.y, R.L, bad);
+  int32_t dz = wrap1(p.z, R.L, bad);
+  if (bad) latch(st, kErrStray);
+  if (dx | dy | dz) {
+    size_t o = 3 * (size_t)id[i];
+    img[o] += dx;
+    img[o + 1] += dy;
+    img[o + 2] += dz;
+  }
+  // most particles stay in the box: write back only a changed position
+  // (a tiny negative coordinate can wrap to L and then to 0 with no net
+  // image change)
+  if (bad || p.x != p0.x || p.y != p0.y || p.z != p0.z) pos[i] = p;
+  int32_t qx = cell_coord(p.x, R.inv_cell, R.nc);
+  int32_t qy = cell_coord(p.y, R.inv_cell, R.nc);
+  int32_t qz = cell_coord(p.z, R.inv_cell, R.nc);
+  return R.coff + (qz * R.nc + qy) * R.nc + qx;
+}
+
 // Wrap + bin.  Particles arrive in the cell order of the previous build, so
 // the lanes of a wave form a few runs of equal cell: one atomic per run
 // reserves the run's slots (the in-cell order is fixed later by the rank
@@ -151,27 +181,7 @@ __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
   const RepDesc R = reps[t.rep];
   int32_t c = -1;
   if (active) {
-    const double4 p0 = pos[i];
-    double4 p = p0;
-    int32_t bad = 0;
-    int32_t dx = wrap1(p.x, R.L, bad);
-    int32_t dy = wrap1(p.y, R.L, bad);
-    int32_t dz = wrap1(p.z, R.L, bad);
-    if (bad) latch(st, kErrStray);
-    if (dx | dy | dz) {
-      size_t o = 3 * (size_t)id[i];
-      img[o] += dx;
-      img[o + 1] += dy;
-      img[o + 2] += dz;
-    }
-    // most particles stay in the box: write back only a changed position
-    // (a tiny negative coordinate can wrap to L and then to 0 with no net
-    // image change)
-    if (bad || p.x != p0.x || p.y != p0.y || p.z != p0.z) pos[i] = p;
-    int32_t qx = cell_coord(p.x, R.inv_cell, R.nc);
-    int32_t qy = cell_coord(p.y, R.inv_cell, R.nc);
-    int32_t qz = cell_coord(p.z, R.inv_cell, R.nc);
-    c = R.coff + (qz * R.nc + qy) * R.nc + qx;
+    c = bin_particle(i, R, pos, id, img, st);
     cell_of[i] = c;
   }
   // runs of equal cell among consecutive active lanes
@@ -417,6 +427,89 @@ __global__ __launch_bounds__(256) void k_cell_gather(
   }
 }
 
+// The whole chain for a context of one replica with at most kSmallN
+// particles and kSmallCells cells, in one block: wrap + bin (histogram in
+// LDS), the exclusive scan, then the ids of every cell in slot order in LDS
+// and each particle's rank among its cell's ids counted there, with a block
+// barrier between the phases.  It leaves the arrays of the launches above
+// (cell_start and the records in the new order) bit for bit: the slots
+// within a cell come out of the atomics in another order, which the rank by
+// id removes.  At this size a launch costs far more than its work, so a
+// step that does not rebuild pays one gated launch instead of four, and the
+// rank runs over all particles at once instead of cell after cell.
+__global__ __launch_bounds__(kSmallThreads) void k_chain_small(
+    const RepDesc* __restrict__ reps, const int32_t* __restrict__ rebuild,
+    double4* __restrict__ pos, const int32_t* __restrict__ id, int32_t* __restrict__ img,
+    int32_t* __restrict__ cell_of, int32_t* __restrict__ slot, int32_t* __restrict__ cell_start,
+    int32_t stride, const double* __restrict__ vel, int32_t* __restrict__ id_tmp,
+    double4* __restrict__ pos_tmp, double* __restrict__ vel_tmp, DevState* st) {
+  __shared__ int32_t s_start[kSmallCells + 1];  // counts, then first particle of each cell
+  __shared__ int32_t s_id[kSmallN];             // ids by cell, then slot
+  __shared__ int32_t s_wsum[kSmallThreads / 64];
+  if (!st->any_rebuild) return;
+  if (!rebuild[0]) return;
+  const RepDesc R = reps[0];
+  const int32_t ncl = R.nc * R.nc * R.nc;
+  const int32_t end = R.off + R.n;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int32_t c = t; c <= ncl; c += kSmallThreads) s_start[c] = 0;
+  __syncthreads();
+  // every phase gives thread t the same particles i, so each reads back
+  // only what it wrote itself (cell_of, slot, the wrapped position)
+  for (int32_t i = R.off + t; i < end; i += kSmallThreads) {
+    const int32_t c = bin_particle(i, R, pos, id, img, st) - R.coff;
+    cell_of[i] = c;
+    slot[i] = atomicAdd(&s_start[c], 1);
+  }
+  __syncthreads();
+  // exclusive scan: thread t holds cells [4t, 4t + 4)
+  int32_t v[4], loc[4], sum = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int32_t c = 4 * t + e;
+    v[e] = c < ncl ? s_start[c] : 0;
+    loc[e] = sum;
+    sum += v[e];
+  }
+  int32_t x = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_wsum[w] = x;
+  __syncthreads();  // also: every count is read before the starts overwrite them
+  int32_t pre = R.off + x - sum, tot = R.off;
+#pragma unroll
+  for (int q = 0; q < kSmallThreads / 64; ++q) {
+    if (q < w) pre += s_wsum[q];
+    tot += s_wsum[q];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int32_t c = 4 * t + e;
+    if (c < ncl) s_start[c] = pre + loc[e];
+  }
+  if (t == 0) s_start[ncl] = tot;
+  __syncthreads();
+  for (int32_t c = t; c <= ncl; c += kSmallThreads) cell_start[R.coff + c] = s_start[c];
+  for (int32_t i = R.off + t; i < end; i += kSmallThreads)
+    s_id[s_start[cell_of[i]] - R.off + slot[i]] = id[i];
+  __syncthreads();
+  for (int32_t i = R.off + t; i < end; i += kSmallThreads) {
+    const int32_t c = cell_of[i], lo = s_start[c] - R.off, hi = s_start[c + 1] - R.off;
+    const int32_t myid = id[i];
+    int32_t rank = 0;
+    for (int32_t m = lo; m < hi; ++m) rank += s_id[m] < myid ? 1 : 0;  // ids are unique
+    const int32_t d = s_start[c] + rank;
+    id_tmp[d] = myid;
+    pos_tmp[d] = pos[i];
+    vel_tmp[d] = vel[i];
+    vel_tmp[stride + d] = vel[stride + i];
+    vel_tmp[2 * (size_t)stride + d] = vel[2 * (size_t)stride + i];
+  }
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -490,6 +583,15 @@ void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int3
   const int32_t grid = spread ? spread_grid(ntiles, spread) : ntiles;
   k_scatter<<<grid, kTile, 0, s>>>(tiles, rebuild, cell_of, slot, cell_start, tmp_src, st,
                                    ntiles, spread);
+}
+
+void launch_chain_small(hipStream_t s, const RepDesc* reps, const int32_t* rebuild,
+                        double4* pos, const int32_t* id, int32_t* img, int32_t* cell_of,
+                        int32_t* slot, int32_t* cell_start, int32_t stride, const double* vel,
+                        int32_t* id_tmp, double4* pos_tmp, double* vel_tmp, DevState* st) {
+  k_chain_small<<<1, kSmallThreads, 0, s>>>(reps, rebuild, pos, id, img, cell_of, slot,
+                                            cell_start, stride, vel, id_tmp, pos_tmp, vel_tmp,
+                                            st);
 }
 
 void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,

@@ -54,6 +54,8 @@ struct md_ctx_s {
   int32_t staged = 0, nrt = 0, lcap_f = 0;
   int32_t cells = 0;  // list-free cell path (row tiles, no neighbour list)
   int32_t any_single = 0, any_multi = 0;  // replicas with one cell / with >= 3 per side
+  bool small_chain = false;  // one small replica: the one-block rebuild chain
+  bool small_list = false;   // ... and the 32-lanes-per-particle list build
   std::vector<RowTile> rtiles_h;
   RowTile* rtiles = nullptr;
   uint16_t* nbr16 = nullptr;
@@ -218,6 +220,7 @@ md_status validate(const md_params* p, std::string* why) {
     return *why = "tile_cells must be 0..64", MD_EINVAL;
   if (p->stage_slots != 0 && p->stage_slots < 64) return *why = "stage_slots must be 0 or >= 64", MD_EINVAL;
   if (p->split_kick != 0 && p->split_kick != 1) return *why = "split_kick must be 0 or 1", MD_EINVAL;
+  if (p->small_box != 0 && p->small_box != 1) return *why = "small_box must be 0 or 1", MD_EINVAL;
   return MD_OK;
 }
 
@@ -246,17 +249,25 @@ md_status sync_and_check(md_ctx c) {
 // step) already cleared the cell histogram (one replica, see
 // launch_kick_drift's nzero and FuseOut)
 void run_chain(md_ctx c, hipStream_t s, bool zeroed = false) {
-  if (!zeroed) launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
   // several replicas rebuild at different steps: spread each one's blocks
   // (bin/scatter: groups of 4 tiles; list build: groups of 32 cells)
   const int32_t spread_t = c->nrep > 1 ? 4 : 0, spread_c = c->nrep > 1 ? 32 : 0;
-  launch_bin(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->pos, c->id, c->img, c->counts,
-             c->cell_of, c->slot, c->st, spread_t);
-  launch_scan(s, c->ncells, c->counts, c->cell_start, c->bsum, c->st);
-  launch_scatter(s, c->ntiles, c->tiles, c->rebuild, c->cell_of, c->slot, c->cell_start,
-                 c->tmp_src, c->st, spread_t);
-  launch_cell_gather(s, c->ncells, c->cell_rep, c->rebuild, c->cell_start, c->tmp_src, c->stride,
-                     c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp, c->st);
+  if (c->small_chain) {
+    // its histogram lives in LDS: nothing to clear
+    launch_chain_small(s, c->reps, c->rebuild, c->pos, c->id, c->img, c->cell_of, c->slot,
+                       c->cell_start, c->stride, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp,
+                       c->st);
+  } else {
+    if (!zeroed) launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
+    launch_bin(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->pos, c->id, c->img, c->counts,
+               c->cell_of, c->slot, c->st, spread_t);
+    launch_scan(s, c->ncells, c->counts, c->cell_start, c->bsum, c->st);
+    launch_scatter(s, c->ntiles, c->tiles, c->rebuild, c->cell_of, c->slot, c->cell_start,
+                   c->tmp_src, c->st, spread_t);
+    launch_cell_gather(s, c->ncells, c->cell_rep, c->rebuild, c->cell_start, c->tmp_src,
+                       c->stride, c->id, c->pos, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp,
+                       c->st);
+  }
   if (c->cells)
     launch_commit_order(s, c->ntiles, c->tiles, c->rebuild, c->stride, c->pos_tmp, c->vel_tmp,
                         c->id_tmp, c->pos, c->vel, c->id, c->xref, c->st);
@@ -265,6 +276,10 @@ void run_chain(md_ctx c, hipStream_t s, bool zeroed = false) {
                        c->cell_start,
                        c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
                        c->xref, c->nbr16, c->ncount, c->st, c->cell_tile, c->rtiles, spread_c);
+  else if (c->small_list && c->any_multi)
+    launch_nlist_small(s, c->ntot, c->reps, c->rebuild, c->tab, c->cell_start, c->stride, c->cap,
+                       c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id, c->xref, c->nbr,
+                       c->ncount, c->st, c->pos16);
   else
     launch_nlist(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->tab, c->thr_form, c->cell_start,
                  c->stride, c->cap, c->pos_tmp, c->vel_tmp, c->id_tmp, c->pos, c->vel, c->id,
@@ -428,8 +443,10 @@ md_status enqueue_step(md_ctx c, hipStream_t s, const ThermoArgs& ta, int32_t th
                        int32_t drift_src = -1) {
   // one replica: its histogram is read only inside a rebuild, so the kick
   // (or the fused force launch before it) clears it when its threads cover
-  // the cells (not in very dilute boxes) and the chain skips a launch
-  const bool zero_in_kick = c->nrep == 1 && (int64_t)c->ncells <= (int64_t)c->ntiles * kTile;
+  // the cells (not in very dilute boxes) and the chain skips a launch (the
+  // one-block chain of a small box keeps its histogram in LDS)
+  const bool zero_in_kick = c->nrep == 1 && !c->small_chain &&
+                            (int64_t)c->ncells <= (int64_t)c->ntiles * kTile;
   const int32_t nzero = zero_in_kick ? c->ncells : 0;
   if (kick && !resume)
     launch_kick_drift(s, c->mixed, thermo, c->ntiles, c->tiles, c->reps, c->tab, c->pos,
@@ -645,6 +662,8 @@ md_status md_init_alloc(md_ctx* out, const md_params* p, int32_t nrep, const int
   }
   c->ncells = coff;
   c->ntiles = tile;
+  c->small_chain = p->small_box == 0 && nrep == 1 && ntot <= kSmallN && c->ncells <= kSmallCells;
+  c->small_list = p->small_box == 0 && nrep == 1 && ntot <= kSmallListN;
 
   // kernel path: the staged path needs >= 3 cells per side in every replica
   bool all3 = true;

@@ -198,6 +198,18 @@ size_t scan_bsum_elems(int32_t ncells);
 void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int32_t* rebuild,
                     const int32_t* cell_of, const int32_t* slot, const int32_t* cell_start,
                     int32_t* tmp_src, const DevState* st, int32_t spread);
+// One-block form of the chain above (zero, bin, scan, scatter, gather) for a
+// context of one replica with at most kSmallN particles and kSmallCells
+// cells; the same cell_start and records, in one launch.  (At 16,384
+// particles the block's serial walk over 16 particles per thread already
+// cost more than the three launches it saves.)
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallN = 8192;
+constexpr int kSmallCells = 4 * kSmallThreads;  // the scan takes four cells per thread
+void launch_chain_small(hipStream_t s, const RepDesc* reps, const int32_t* rebuild,
+                        double4* pos, const int32_t* id, int32_t* img, int32_t* cell_of,
+                        int32_t* slot, int32_t* cell_start, int32_t stride, const double* vel,
+                        int32_t* id_tmp, double4* pos_tmp, double* vel_tmp, DevState* st);
 void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* rebuild, const int32_t* cell_start,
                         const int32_t* tmp_src, int32_t stride, const int32_t* id,
@@ -227,6 +239,18 @@ void launch_nlist(hipStream_t s, int32_t ntiles, const Tile* tiles, const RepDes
                   uint32_t* nbr, int32_t* ncount, DevState* st, int32_t ncells,
                   const int32_t* cell_rep, int32_t any_single, int32_t any_multi,
                   int4* pos16, int32_t spread);
+// The gather-path search of a one-replica context with at most
+// kSmallListN particles and >= 3 cells per side: the rows of launch_nlist
+// bit for bit, 32 lanes per home particle instead of one wave per cell.
+// (From ~16,000 particles on the box has cells enough for the one-wave-per-
+// cell search to fill the chip: at 32,000 it is the faster one.)
+constexpr int kSmallListN = 16384;
+void launch_nlist_small(hipStream_t s, int32_t ntot, const RepDesc* reps,
+                        const int32_t* rebuild, const PairTab* tab, const int32_t* cell_start,
+                        int32_t stride, int32_t cap, const double4* pos_tmp,
+                        const double* vel_tmp, const int32_t* id_tmp, double4* pos, double* vel,
+                        int32_t* id, double* xref, uint32_t* nbr, int32_t* ncount, DevState* st,
+                        int4* pos16);
 // force.hip
 // mode 0: forces + PE/W + KE of the current v;  mode 1: also the second
 // half kick v += dt/2 F/m before KE, and PE/W only when energy != 0;

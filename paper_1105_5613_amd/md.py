@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("dt", C.c_double), ("max_neighbors", C.c_int32), ("graph_steps", C.c_int32),
                 ("tpp", C.c_int32), ("unroll", C.c_int32),
                 ("path", C.c_int32), ("tile_cells", C.c_int32), ("stage_slots", C.c_int32),
-                ("split_kick", C.c_int32)]
+                ("split_kick", C.c_int32), ("small_box", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -115,7 +115,7 @@ def lib():
 def make_params(eps, sig, rc, mass, *, skin=0.3, dt=0.005, precision=MD_FP64,
                 potential=MD_POT_LJ, trunc=MD_TRUNC_SHIFTED_FORCE, max_neighbors=0,
                 graph_steps=0, tpp=0, unroll=0, path=MD_PATH_AUTO, tile_cells=0,
-                stage_slots=0, split_kick=0) -> Params:
+                stage_slots=0, split_kick=0, small_box=0) -> Params:
     p = Params()
     nt = len(eps)
     p.ntypes = nt
@@ -138,6 +138,7 @@ def make_params(eps, sig, rc, mass, *, skin=0.3, dt=0.005, precision=MD_FP64,
     p.tile_cells = int(tile_cells)
     p.stage_slots = int(stage_slots)
     p.split_kick = int(split_kick)
+    p.small_box = int(small_box)
     return p
 
 

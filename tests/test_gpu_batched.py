@@ -122,7 +122,11 @@ def test_batched_steps_match_oracle_per_replica(torch_cuda, precision):
 
 def test_batched_equals_one_context_per_replica(torch_cuda):
     """The batch and the replicas run alone (same graphs and thermostat) give
-    the same bits: positions, velocities, image counters and every log."""
+    the same bits: positions, velocities, image counters and every log.  A
+    context of one replica of at most 8,192 particles rebuilds with the
+    one-block chain and the 32-lane list build, one of at most 16,384 with
+    the latter (13,500 here), the batch with the general kernels: this also
+    holds those to the general ones bit for bit."""
     from paper_1105_5613_amd import System
     say("case batched vs one context per replica")
     systems, (x, v, t, n, L) = replicas()

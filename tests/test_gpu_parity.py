@@ -86,20 +86,22 @@ def test_cells_lists_forces_fp64(torch_cuda, n, seed, kw):
     assert ob["n_rebuild"] == 1
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_dense_cells_groups_and_passes(torch_cuda, precision):
+@pytest.mark.parametrize("precision,small_box", [(0, 1), (1, 1), (0, 0), (1, 0)])
+def test_dense_cells_groups_and_passes(torch_cuda, precision, small_box):
     """One cutoff of 3.0 for every pair in a 2,048-particle box: 3 cells per
-    side of ~4.0, ~76 particles per cell, so the list build takes each cell's
-    home particles in three groups, and the 27-cell neighbourhood is the
-    whole box (2,048 candidates: three passes of chunks, the later ones
-    starting at each home's running count).  Lists bit-exact (canonical),
-    forces within the bar, before and after steps."""
+    side of ~4.0, ~76 particles per cell, so the general list build takes
+    each cell's home particles in three groups, and the 27-cell neighbourhood
+    is the whole box (2,048 candidates: three passes of chunks, the later
+    ones starting at each home's running count); the small-box kernels
+    (small_box = 0) sort cells of more than 64 particles and walk 76-particle
+    stencil cells per lane.  Lists bit-exact (canonical), forces within the
+    bar, before and after steps."""
     from paper_1105_5613_amd import System, make_params
-    say(f"case dense cells precision={precision}")
+    say(f"case dense cells precision={precision} small_box={small_box}")
     eps, sig, rc, mass = initconf.mixture_tables(global_rc=3.0)
     s = initconf.fcc_system(2048, seed=31, temperature=1.5)
-    sysm = System(make_params(eps, sig, rc, mass, skin=SKIN, dt=0.005, precision=precision),
-                  [2048], [s["L"]])
+    sysm = System(make_params(eps, sig, rc, mass, skin=SKIN, dt=0.005, precision=precision,
+                              small_box=small_box), [2048], [s["L"]])
     sysm.set_state(s["x"], s["v"], s["type"])
     po = oracle.make_params(eps, sig, rc, mass, skin=SKIN)
     for k in range(2):
@@ -148,15 +150,18 @@ def boundary_state(seed):
     return s, x, int(near.sum())
 
 
-@pytest.mark.parametrize("precision,path", [(0, 1), (0, 2), (1, 1), (0, 3)])
-def test_cell_faces_and_wrap_cases(torch_cuda, precision, path):
+@pytest.mark.parametrize("precision,path,small_box", [(0, 1, 0), (0, 1, 1), (0, 2, 0), (1, 1, 0),
+                                                       (1, 1, 1), (0, 3, 0)])
+def test_cell_faces_and_wrap_cases(torch_cuda, precision, path, small_box):
     """Particles exactly on cell faces and at the wrap edge cases: wrapped
     positions, image counters, cell arrays and lists bit-exact, forces within
-    the bar."""
+    the bar (small_box = 1: the general kernels at this size)."""
     from paper_1105_5613_amd import System
     s, x, nsnap = boundary_state(31)
-    say(f"case cell faces precision={precision} path={path}: {nsnap} coordinates on faces")
-    sysm = System(lib_params(precision=precision, path=path), [4000], [s["L"]])
+    say(f"case cell faces precision={precision} path={path} small_box={small_box}: "
+        f"{nsnap} coordinates on faces")
+    sysm = System(lib_params(precision=precision, path=path, small_box=small_box), [4000],
+                  [s["L"]])
     sysm.set_state(x, s["v"], s["type"])
     sysm.build_cells()
     p = oracle_params()
@@ -209,15 +214,19 @@ def threshold_pairs():
     return np.array(xs), np.array(ts, dtype=np.int32), L
 
 
-@pytest.mark.parametrize("precision,path", [(0, 1), (0, 2), (1, 1)])
-def test_list_threshold_ties(torch_cuda, precision, path):
+@pytest.mark.parametrize("precision,path,small_box", [(0, 1, 0), (0, 1, 1), (0, 2, 0), (1, 1, 0),
+                                                       (1, 1, 1)])
+def test_list_threshold_ties(torch_cuda, precision, path, small_box):
     """Pairs at r^2 just below, equal to and just above (r_c,ab + skin)^2: the
-    strict inclusion test gives bit-identical lists to the oracle's."""
+    strict inclusion test gives bit-identical lists to the oracle's, in the
+    small-box search (which reads the threshold table) and in the general one
+    (which forms the threshold from the home species, small_box = 1)."""
     from paper_1105_5613_amd import System
     x, types, L = threshold_pairs()
     n = len(x)
-    say(f"case threshold ties precision={precision} path={path}: {n // 2} pairs")
-    sysm = System(lib_params(precision=precision, path=path), [n], [L])
+    say(f"case threshold ties precision={precision} path={path} small_box={small_box}: "
+        f"{n // 2} pairs")
+    sysm = System(lib_params(precision=precision, path=path, small_box=small_box), [n], [L])
     sysm.set_state(x, np.zeros_like(x), types)
     sysm.build_cells()
     p = oracle_params()
@@ -254,6 +263,8 @@ def test_dilute_box_cells_after_steps(torch_cuda):
 # threshold either as one FMA over the home species value (one species, or two
 # whose thresholds for each partner species lie within a factor of two) or by
 # a select chain: "one" takes the first form, "two-wide" and "three" the second.
+# At 13,500 particles a one-box context searches with the small-box kernel,
+# which reads the threshold table directly; small_box = 1 runs the general one.
 SPECIES_TABLES = {
     "one": ([[1.0]], [[1.0]], [[2.5]], [1.0]),
     "two-wide": ([[1.0, 1.5], [1.5, 0.5]], [[1.0, 0.7], [0.7, 0.4]],
@@ -264,20 +275,21 @@ SPECIES_TABLES = {
 }
 
 
-@pytest.mark.parametrize("name,precision,path", [
-    ("one", 0, 1), ("two-wide", 0, 1), ("two-wide", 0, 2), ("three", 0, 1), ("three", 0, 2),
-    ("three", 1, 1)])
-def test_species_tables(torch_cuda, name, precision, path):
+@pytest.mark.parametrize("name,precision,path,small_box", [
+    ("one", 0, 1, 0), ("one", 0, 1, 1), ("two-wide", 0, 1, 0), ("two-wide", 0, 1, 1),
+    ("two-wide", 0, 2, 0), ("three", 0, 1, 0), ("three", 0, 1, 1), ("three", 0, 2, 0),
+    ("three", 1, 1, 0), ("three", 1, 1, 1)])
+def test_species_tables(torch_cuda, name, precision, path, small_box):
     from paper_1105_5613_amd import System, make_params
-    say(f"case species table {name} precision={precision} path={path}")
+    say(f"case species table {name} precision={precision} path={path} small_box={small_box}")
     eps, sig, rc, mass = SPECIES_TABLES[name]
     n = 13500
     s = initconf.fcc_system(n, seed=21, temperature=1.0)
     nt = len(eps)
     types = np.random.default_rng(22).integers(0, nt, n).astype(np.int32) if nt != 2 \
         else s["type"]
-    sysm = System(make_params(eps, sig, rc, mass, skin=0.3, precision=precision, path=path),
-                  [n], [s["L"]])
+    sysm = System(make_params(eps, sig, rc, mass, skin=0.3, precision=precision, path=path,
+                              small_box=small_box), [n], [s["L"]])
     sysm.set_state(s["x"], s["v"], types)
     p = oracle.make_params(eps, sig, rc, mass, skin=0.3)
     sysm.build_cells()
@@ -516,6 +528,10 @@ def test_error_paths(torch_cuda):
     # unknown kick mode
     with pytest.raises(MDError) as ex:
         System(lib_params(split_kick=2), [500], [s["L"]])
+    assert ex.value.code == -1
+    # unknown small-box mode
+    with pytest.raises(MDError) as ex:
+        System(lib_params(small_box=2), [500], [s["L"]])
     assert ex.value.code == -1
     # bad species
     sysm = System(lib_params(), [500], [s["L"]])
