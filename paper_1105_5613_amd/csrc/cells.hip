@@ -124,15 +124,14 @@ __device__ inline int32_t cell_coord(double c, double inv_cell, int32_t nc) {
   return q > nc - 1 ? nc - 1 : q;
 }
 
-// Wrap particle i of replica R into the box (image counter and position
-// updated; a coordinate that one wrap does not bring into [0, L) latches
-// kErrStray) and return its cell, numbered from the first cell of all
-// replicas.
-__device__ inline int32_t bin_particle(int32_t i, const RepDesc& R, double4* __restrict__ pos,
-                                       const int32_t* __restrict__ id, int32_t* __restrict__ img,
-                                       DevState* st) {
-  const double4 p0 = pos[i];
-  double4 p = p0;
+// Wrap particle i of replica R, whose position p was just read from pos[i],
+// into the box (p, pos[i] and the image counter updated; a coordinate that
+// one wrap does not bring into [0, L) latches kErrStray) and return its
+// cell, numbered from the first cell of all replicas.
+__device__ inline int32_t bin_particle(int32_t i, double4& p, const RepDesc& R,
+                                       double4* __restrict__ pos, const int32_t* __restrict__ id,
+                                       int32_t* __restrict__ img, DevState* st) {
+  const double4 p0 = p;
   int32_t bad = 0;
   int32_t dx = wrap1(p.x, R.L, bad);
   int32_t dy = wrap1(p.y, R.L, bad);
@@ -181,7 +180,8 @@ __global__ __launch_bounds__(kTile) void k_bin(const Tile* __restrict__ tiles,
   const RepDesc R = reps[t.rep];
   int32_t c = -1;
   if (active) {
-    c = bin_particle(i, R, pos, id, img, st);
+    double4 p = pos[i];
+    c = bin_particle(i, p, R, pos, id, img, st);
     cell_of[i] = c;
   }
   // runs of equal cell among consecutive active lanes
@@ -435,14 +435,17 @@ __global__ __launch_bounds__(256) void k_cell_gather(
 // (cell_start and the records in the new order) bit for bit: the slots
 // within a cell come out of the atomics in another order, which the rank by
 // id removes.  At this size a launch costs far more than its work, so a
-// step that does not rebuild pays one gated launch instead of four, and the
-// rank runs over all particles at once instead of cell after cell.
+// step that does not rebuild pays one gated launch instead of four.  Thread
+// t takes particles t, t + 1024, ... (at most kSmallN / kSmallThreads) in
+// every phase, keeps their cells, slots and ids in registers, and reads the
+// records of all of them with one round trip per phase.
 __global__ __launch_bounds__(kSmallThreads) void k_chain_small(
     const RepDesc* __restrict__ reps, const int32_t* __restrict__ rebuild,
     double4* __restrict__ pos, const int32_t* __restrict__ id, int32_t* __restrict__ img,
-    int32_t* __restrict__ cell_of, int32_t* __restrict__ slot, int32_t* __restrict__ cell_start,
-    int32_t stride, const double* __restrict__ vel, int32_t* __restrict__ id_tmp,
-    double4* __restrict__ pos_tmp, double* __restrict__ vel_tmp, DevState* st) {
+    int32_t* __restrict__ cell_start, int32_t stride, const double* __restrict__ vel,
+    int32_t* __restrict__ id_tmp, double4* __restrict__ pos_tmp, double* __restrict__ vel_tmp,
+    DevState* st) {
+  constexpr int kPer = kSmallN / kSmallThreads;
   __shared__ int32_t s_start[kSmallCells + 1];  // counts, then first particle of each cell
   __shared__ int32_t s_id[kSmallN];             // ids by cell, then slot
   __shared__ int32_t s_wsum[kSmallThreads / 64];
@@ -453,13 +456,29 @@ __global__ __launch_bounds__(kSmallThreads) void k_chain_small(
   const int32_t end = R.off + R.n;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int32_t c = t; c <= ncl; c += kSmallThreads) s_start[c] = 0;
-  __syncthreads();
-  // every phase gives thread t the same particles i, so each reads back
-  // only what it wrote itself (cell_of, slot, the wrapped position)
-  for (int32_t i = R.off + t; i < end; i += kSmallThreads) {
-    const int32_t c = bin_particle(i, R, pos, id, img, st) - R.coff;
-    cell_of[i] = c;
-    slot[i] = atomicAdd(&s_start[c], 1);
+  int32_t idv[kPer], cl[kPer], sl[kPer];
+  {
+    double4 pv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int32_t i = R.off + t + u * kSmallThreads;
+      if (i < end) {
+        pv[u] = pos[i];
+        idv[u] = id[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int32_t i = R.off + t + u * kSmallThreads;
+      cl[u] = 0;
+      sl[u] = 0;
+      if (i < end) {
+        // writes the wrapped position back to pos[i] when it changed
+        cl[u] = bin_particle(i, pv[u], R, pos, id, img, st) - R.coff;
+        sl[u] = atomicAdd(&s_start[cl[u]], 1);
+      }
+    }
   }
   __syncthreads();
   // exclusive scan: thread t holds cells [4t, 4t + 4)
@@ -493,20 +512,24 @@ __global__ __launch_bounds__(kSmallThreads) void k_chain_small(
   if (t == 0) s_start[ncl] = tot;
   __syncthreads();
   for (int32_t c = t; c <= ncl; c += kSmallThreads) cell_start[R.coff + c] = s_start[c];
-  for (int32_t i = R.off + t; i < end; i += kSmallThreads)
-    s_id[s_start[cell_of[i]] - R.off + slot[i]] = id[i];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    if (R.off + t + u * kSmallThreads < end) s_id[s_start[cl[u]] - R.off + sl[u]] = idv[u];
   __syncthreads();
-  for (int32_t i = R.off + t; i < end; i += kSmallThreads) {
-    const int32_t c = cell_of[i], lo = s_start[c] - R.off, hi = s_start[c + 1] - R.off;
-    const int32_t myid = id[i];
-    int32_t rank = 0;
-    for (int32_t m = lo; m < hi; ++m) rank += s_id[m] < myid ? 1 : 0;  // ids are unique
-    const int32_t d = s_start[c] + rank;
-    id_tmp[d] = myid;
-    pos_tmp[d] = pos[i];
-    vel_tmp[d] = vel[i];
-    vel_tmp[stride + d] = vel[stride + i];
-    vel_tmp[2 * (size_t)stride + d] = vel[2 * (size_t)stride + i];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int32_t i = R.off + t + u * kSmallThreads;
+    if (i < end) {
+      const int32_t lo = s_start[cl[u]] - R.off, hi = s_start[cl[u] + 1] - R.off;
+      int32_t rank = 0;
+      for (int32_t m = lo; m < hi; ++m) rank += s_id[m] < idv[u] ? 1 : 0;  // ids are unique
+      const int32_t d = R.off + lo + rank;
+      id_tmp[d] = idv[u];
+      pos_tmp[d] = pos[i];  // this thread's own write-back, if any
+      vel_tmp[d] = vel[i];
+      vel_tmp[stride + d] = vel[stride + i];
+      vel_tmp[2 * (size_t)stride + d] = vel[2 * (size_t)stride + i];
+    }
   }
 }
 
@@ -586,12 +609,11 @@ void launch_scatter(hipStream_t s, int32_t ntiles, const Tile* tiles, const int3
 }
 
 void launch_chain_small(hipStream_t s, const RepDesc* reps, const int32_t* rebuild,
-                        double4* pos, const int32_t* id, int32_t* img, int32_t* cell_of,
-                        int32_t* slot, int32_t* cell_start, int32_t stride, const double* vel,
-                        int32_t* id_tmp, double4* pos_tmp, double* vel_tmp, DevState* st) {
-  k_chain_small<<<1, kSmallThreads, 0, s>>>(reps, rebuild, pos, id, img, cell_of, slot,
-                                            cell_start, stride, vel, id_tmp, pos_tmp, vel_tmp,
-                                            st);
+                        double4* pos, const int32_t* id, int32_t* img, int32_t* cell_start,
+                        int32_t stride, const double* vel, int32_t* id_tmp, double4* pos_tmp,
+                        double* vel_tmp, DevState* st) {
+  k_chain_small<<<1, kSmallThreads, 0, s>>>(reps, rebuild, pos, id, img, cell_start, stride,
+                                            vel, id_tmp, pos_tmp, vel_tmp, st);
 }
 
 void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,

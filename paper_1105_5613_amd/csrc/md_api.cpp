@@ -254,9 +254,8 @@ void run_chain(md_ctx c, hipStream_t s, bool zeroed = false) {
   const int32_t spread_t = c->nrep > 1 ? 4 : 0, spread_c = c->nrep > 1 ? 32 : 0;
   if (c->small_chain) {
     // its histogram lives in LDS: nothing to clear
-    launch_chain_small(s, c->reps, c->rebuild, c->pos, c->id, c->img, c->cell_of, c->slot,
-                       c->cell_start, c->stride, c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp,
-                       c->st);
+    launch_chain_small(s, c->reps, c->rebuild, c->pos, c->id, c->img, c->cell_start, c->stride,
+                       c->vel, c->id_tmp, c->pos_tmp, c->vel_tmp, c->st);
   } else {
     if (!zeroed) launch_zero_counts(s, c->ncells, c->cell_rep, c->rebuild, c->st, c->counts);
     launch_bin(s, c->ntiles, c->tiles, c->reps, c->rebuild, c->pos, c->id, c->img, c->counts,

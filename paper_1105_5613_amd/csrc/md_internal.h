@@ -207,9 +207,9 @@ constexpr int kSmallThreads = 1024;
 constexpr int kSmallN = 8192;
 constexpr int kSmallCells = 4 * kSmallThreads;  // the scan takes four cells per thread
 void launch_chain_small(hipStream_t s, const RepDesc* reps, const int32_t* rebuild,
-                        double4* pos, const int32_t* id, int32_t* img, int32_t* cell_of,
-                        int32_t* slot, int32_t* cell_start, int32_t stride, const double* vel,
-                        int32_t* id_tmp, double4* pos_tmp, double* vel_tmp, DevState* st);
+                        double4* pos, const int32_t* id, int32_t* img, int32_t* cell_start,
+                        int32_t stride, const double* vel, int32_t* id_tmp, double4* pos_tmp,
+                        double* vel_tmp, DevState* st);
 void launch_cell_gather(hipStream_t s, int32_t ncells, const int32_t* cell_rep,
                         const int32_t* rebuild, const int32_t* cell_start,
                         const int32_t* tmp_src, int32_t stride, const int32_t* id,
