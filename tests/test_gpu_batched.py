@@ -120,7 +120,8 @@ def test_batched_steps_match_oracle_per_replica(torch_cuda, precision):
         off += nr
 
 
-def test_batched_equals_one_context_per_replica(torch_cuda):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_equals_one_context_per_replica(torch_cuda, precision):
     """The batch and the replicas run alone (same graphs and thermostat) give
     the same bits: positions, velocities, image counters and every log.  A
     context of one replica of at most 8,192 particles rebuilds with the
@@ -128,9 +129,9 @@ def test_batched_equals_one_context_per_replica(torch_cuda):
     the latter (13,500 here), the batch with the general kernels: this also
     holds those to the general ones bit for bit."""
     from paper_1105_5613_amd import System
-    say("case batched vs one context per replica")
+    say(f"case batched vs one context per replica, precision={precision}")
     systems, (x, v, t, n, L) = replicas()
-    sysm = System(lib_params(graph_steps=10), n, L)
+    sysm = System(lib_params(precision=precision, graph_steps=10), n, L)
     sysm.set_state(x, v, t)
     log = sysm.step(STEPS, T0=TEMPS, log_every=3)
     log2 = sysm.step(12, T0=TEMPS, T1=[1.0] * len(SIZES), ramp=10, log_every=4)
@@ -138,7 +139,7 @@ def test_batched_equals_one_context_per_replica(torch_cuda):
     off = 0
     for r, sy in enumerate(systems):
         nr = sy["n"]
-        one = System(lib_params(graph_steps=10), [nr], [sy["L"]])
+        one = System(lib_params(precision=precision, graph_steps=10), [nr], [sy["L"]])
         one.set_state(sy["x"], sy["v"], sy["type"])
         la = one.step(STEPS, T0=[TEMPS[r]], log_every=3)
         lb = one.step(12, T0=[TEMPS[r]], T1=[1.0], ramp=10, log_every=4)
