@@ -44,6 +44,7 @@ LIST_SRC = os.path.join(ROOT, "paper_1105_5613_amd", "csrc", "nlist.hip")
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "force_counters.json")
 FP64_OPS_JSON = os.path.join(ROOT, "profiles", "fp64_ops.json")
 FP64_PEAK_TFLOPS = 78.6
+LARGE_N = 67108864  # the large mixed form; its counters hold for this size only
 CSRC = os.path.join(ROOT, "paper_1105_5613_amd", "csrc")
 # kernels whose FP64 operation counts the bench turns into FLOP/s: name
 # fragment in the counter output -> source file
@@ -428,10 +429,15 @@ def counters_summary(args):
            "copy_bytes": COPY_BYTES, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "copy_factor_fetch": copy_kib / cf, "copy_factor_write": copy_kib / cw,
            "forms": {}, "commands": args.commands}
-    for form, key in (("fp64", "k_force<false, 2"), ("mixed", "k_force<true, 2")):
+    runs = [("fp64", "k_force<false, 2", args.fetch_dir, args.write_dir),
+            ("mixed", "k_force<true, 2", args.fetch_dir, args.write_dir)]
+    if args.large_fetch_dir and args.large_write_dir:
+        runs.append(("large_mixed", "k_force<true, 2", args.large_fetch_dir,
+                     args.large_write_dir))
+    for form, key, fdir, wdir in runs:
         try:
-            f, nf = mean_for(args.fetch_dir, "k_force", "FETCH_SIZE", key)
-            w, nw = mean_for(args.write_dir, "k_force", "WRITE_SIZE", key)
+            f, nf = mean_for(fdir, "k_force", "FETCH_SIZE", key)
+            w, nw = mean_for(wdir, "k_force", "WRITE_SIZE", key)
         except ZeroDivisionError:
             continue
         out["forms"][form] = {"fetch_kib": f, "write_kib": w, "dispatches": nf}
@@ -456,7 +462,7 @@ def main():
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=2000)
-    ap.add_argument("--large-n", type=int, default=67108864)
+    ap.add_argument("--large-n", type=int, default=LARGE_N)
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--serial-steps", type=int, default=50)
     ap.add_argument("--graph-steps", type=int, default=100,
@@ -470,6 +476,8 @@ def main():
     ap.add_argument("--write-dir")
     ap.add_argument("--copy-fetch-dir")
     ap.add_argument("--copy-write-dir")
+    ap.add_argument("--large-fetch-dir")
+    ap.add_argument("--large-write-dir")
     ap.add_argument("--commands", default="")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -554,6 +562,7 @@ def main():
         del big
         bl = force_bytes_per_particle(rl["nbar"], True)
         ach = gbs(nl * bl, rl["force_ms_avg"])
+        trl = counters_traffic("large_mixed") if nl == LARGE_N else None
         log(f"  large mixed: {rl['rate']:.4e} particle-steps/s, {rl['ms_per_step']:.3f} ms/step, "
             f"force {rl['force_ms_avg']} ms")
         forms_out["large_mixed"] = {
@@ -562,6 +571,8 @@ def main():
             "value": round(rl["rate"], 1), "ms_per_step": round(rl["ms_per_step"], 4),
             "force_ms_avg": rnd(rl["force_ms_avg"], 4), "force_achieved_gbs": rnd(ach, 1),
             "force_frac_hbm": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
+            "force_traffic_bytes": None if trl is None else round(trl),
+            "force_traffic_over_algorithmic": None if trl is None else round(trl / (nl * bl), 3),
             "mean_list_length": round(rl["nbar"], 3), "rebuilds": rl["rebuilds"],
             "energy_drift_per_particle_per_1000_steps": (rl["drift"] or {}).get("D"),
             "energy_drift": rl["drift"], "tuned": rl["tuned"]}
