@@ -1,6 +1,6 @@
 """Host-side logic of bench.py (no GPU): the algorithmic byte accounting of
 the force launch and the whole step, the drift estimator, the counter-traffic
-guard and the one-GPU guard."""
+guard, the counter summary per form and the one-GPU guard."""
 import json
 import os
 import subprocess
@@ -69,6 +69,49 @@ def test_counter_traffic_needs_the_current_kernel_source(tmp_path, monkeypatch):
         e[key] = "0" * 64
         p.write_text(json.dumps(e))
         assert bench.counters_traffic("fp64") is None
+
+
+def _write_counters(d, rows):
+    """A rocprofv3 --pmc counter_collection.csv with the given (kernel, counter, value) rows."""
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w") as f:
+        f.write("Kernel_Name,Counter_Name,Counter_Value\n")
+        for k, c, v in rows:
+            f.write(f'"{k}",{c},{v}\n')
+
+
+def test_counters_summary_per_form(tmp_path, monkeypatch):
+    # the 1M runs give fp64 and mixed (the in-step mode-2 launches only), the
+    # 67M run the large mixed form; each counter is scaled by the copy's
+    fp64 = "void mdk::k_force<false, 2, 2, 4, false, true>(int)"
+    mixed = "void mdk::k_force<true, 2, 1, 8, false, true>(int)"
+    tuner = "void mdk::k_force<false, 0, 2, 4, true, true>(int)"
+    copy = "__amd_rocclr_copyBuffer"
+    t = str(tmp_path)
+    _write_counters(t + "/f", [(fp64, "FETCH_SIZE", 100.0), (fp64, "FETCH_SIZE", 300.0),
+                               (mixed, "FETCH_SIZE", 50.0), (tuner, "FETCH_SIZE", 1e9)])
+    _write_counters(t + "/w", [(fp64, "WRITE_SIZE", 10.0), (mixed, "WRITE_SIZE", 20.0)])
+    _write_counters(t + "/cf", [(copy, "FETCH_SIZE", 524288.0)])
+    _write_counters(t + "/cw", [(copy, "WRITE_SIZE", 1048576.0)])
+    _write_counters(t + "/lf", [(mixed, "FETCH_SIZE", 7000.0)])
+    _write_counters(t + "/lw", [(mixed, "WRITE_SIZE", 900.0)])
+    out = tmp_path / "c.json"
+    monkeypatch.setattr(bench, "COUNTERS_JSON", str(out))
+    args = type("A", (), dict(fetch_dir=t + "/f", write_dir=t + "/w", copy_fetch_dir=t + "/cf",
+                              copy_write_dir=t + "/cw", large_fetch_dir=t + "/lf",
+                              large_write_dir=t + "/lw", commands="test"))()
+    bench.counters_summary(args)
+    d = json.loads(out.read_text())
+    assert d["copy_factor_fetch"] == pytest.approx(2.0)
+    assert d["copy_factor_write"] == pytest.approx(1.0)
+    assert d["forms"]["fp64"] == {"fetch_kib": 200.0, "write_kib": 10.0, "dispatches": 2}
+    assert d["forms"]["mixed"]["fetch_kib"] == 50.0
+    assert d["forms"]["large_mixed"] == {"fetch_kib": 7000.0, "write_kib": 900.0, "dispatches": 1}
+    assert bench.counters_traffic("large_mixed") == pytest.approx((7000.0 * 2.0 + 900.0) * 1024)
+    # without the 67M runs the large form has no counters
+    args.large_fetch_dir = None
+    bench.counters_summary(args)
+    assert "large_mixed" not in json.loads(out.read_text())["forms"]
 
 
 def test_more_than_one_gpu_is_refused():
